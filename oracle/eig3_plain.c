@@ -1,0 +1,236 @@
+/*
+ * eig3_plain.c -- the paper's algorithms in plain binary64 C, one matrix at a
+ * time.
+ *
+ * TEST INFRASTRUCTURE.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  It shares no code,
+ * header or constant with the HIP library.
+ *
+ * Habera & Zilian, "Numerically stable evaluation of closed-form expressions
+ * for eigenvalues of 3x3 matrices" (arXiv 2511.00292):
+ *   I1     -- Alg. alg:I1-stable     (Sec. "Invariant I1")
+ *   J2     -- Alg. alg:J2-stable     (Sec. "Invariant J2")
+ *   J3     -- Alg. alg:J3-stable     (Sec. "Invariant J3")
+ *   Delta  -- Alg. alg:disc-stable   (Sec. "Discriminant"), sum of products
+ *             of the auxiliary vectors u = dx(A), v = dx(A^T) with weights w
+ *   lambda -- Alg. alg:eigvals-stable (Sec. "Eigenvalues") with the
+ *             trigonometric formula Eq. eigvals-trig.
+ *
+ * Readings where the printed text is silent or inconsistent:
+ *   - r10 of dx: printed with "- M02 M21 d2"; the sum of products only equals
+ *     4 J2^3 - 27 J3^2 with "+ M02 M21 d2", which is used here.
+ *   - the triple angle is atan2(sqrt(27 Delta), 27 J3) in [0, pi], the branch
+ *     that equals arccos((3 sqrt3 / 2) J3 / J2^(3/2)) of Eq. eigvals-trig's
+ *     definition of phi; a plain arctan of the quotient is wrong for J3 < 0.
+ *   - Delta < 0 and J2 < 0 (possible after rounding for nonsymmetric input)
+ *     are clamped to 0 before the square roots.
+ *   - the three values are sorted ascending at the end (ties may swap by an
+ *     ulp otherwise).
+ *   - the fractions 1/3, 1/6, 1/27 are divisions, sums run left to right as
+ *     printed, and the file is built with -ffp-contract=off (no FMA).
+ *
+ * Backward (vector-Jacobian product) follows the eigenprojector relation
+ * d(lambda_k)/dA = E_k^T of Sec. "Introduction and motivation", with the
+ * Frobenius covariant E_k = (A - l_i I)(A - l_j I) / ((l_k - l_i)(l_k - l_j)),
+ * a route that does not go through the invariants.
+ *
+ * Matrices are stored row-major, 9 doubles per matrix (A00 A01 A02 A10 ...).
+ */
+#include <math.h>
+#include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- Alg. 1 */
+static double alg_I1(const double *A)
+{
+    return A[0] + A[4] + A[8];
+}
+
+/* ---------------------------------------------------------------- Alg. 2 */
+static double alg_J2(const double *A)
+{
+    const double A00 = A[0], A01 = A[1], A02 = A[2];
+    const double A10 = A[3], A11 = A[4], A12 = A[5];
+    const double A20 = A[6], A21 = A[7], A22 = A[8];
+    double d0 = A00 - A11, d1 = A00 - A22, d2 = A11 - A22;
+    double offdiag = A01 * A10 + A02 * A20 + A12 * A21;
+    double diag = (d0 * d0 + d1 * d1 + d2 * d2) / 6.0;
+    return diag + offdiag;
+}
+
+/* ---------------------------------------------------------------- Alg. 5 */
+static double alg_J3(const double *A)
+{
+    const double A00 = A[0], A01 = A[1], A02 = A[2];
+    const double A10 = A[3], A11 = A[4], A12 = A[5];
+    const double A20 = A[6], A21 = A[7], A22 = A[8];
+    double d0 = A00 - A11, d1 = A00 - A22, d2 = A11 - A22;
+    double t1 = d1 + d2;
+    double t2 = d0 - d2;
+    double t3 = -d0 - d1;
+    double offdiag = A01 * A12 * A20 + A02 * A10 * A21;
+    double mixed = (A01 * A10 * t1 + A02 * A20 * t2 + A12 * A21 * t3) / 3.0;
+    double diag = t1 * t2 * t3 / 27.0;
+    return offdiag + mixed - diag;
+}
+
+/* ---------------------------------------------------------------- Alg. 8 */
+/* the auxiliary vector dx(M; d0, d1, d2), 14 entries r1..r14 stored at r[0..13] */
+static void alg_dx(const double *M, double d0, double d1, double d2, double *r)
+{
+    const double M01 = M[1], M02 = M[2];
+    const double M10 = M[3], M12 = M[5];
+    const double M20 = M[6], M21 = M[7];
+    r[0] = M01 * M12 * M20 - M02 * M10 * M21;
+    r[1] = -M01 * M02 * d2 + M01 * M01 * M12 - M02 * M02 * M21;
+    r[2] = M01 * M21 * d1 - M01 * M01 * M20 + M02 * M21 * M21;
+    r[3] = M02 * M12 * d0 + M01 * M12 * M12 - M02 * M02 * M10;
+    r[4] = M01 * M12 * d1 - M01 * M02 * M10 + M02 * M12 * M21;
+    r[5] = M02 * M21 * d0 - M01 * M02 * M20 + M01 * M12 * M21;
+    r[6] = -M02 * M10 * d2 + M01 * M10 * M12 - M02 * M12 * M20;
+    r[7] = M12 * d0 * d1 - M02 * M10 * d1 + M01 * M10 * M12 - M12 * M12 * M21;
+    r[8] = M12 * d0 * d1 - M02 * M10 * d0 + M02 * M12 * M20 - M12 * M12 * M21;
+    r[9] = M01 * d1 * d2 + M02 * M21 * d2 + M01 * M02 * M20 - M01 * M01 * M10; /* sign read as + */
+    r[10] = M01 * d1 * d2 + M02 * M21 * d1 + M01 * M12 * M21 - M01 * M01 * M10;
+    r[11] = -M02 * d0 * d2 + M01 * M12 * d0 + M02 * M12 * M21 - M02 * M02 * M20;
+    r[12] = M02 * d0 * d2 + M01 * M12 * d2 - M01 * M02 * M10 + M02 * M02 * M20;
+    r[13] = d0 * d1 * d2 - M01 * M10 * d0 + M02 * M20 * d1 - M12 * M21 * d2;
+}
+
+static double alg_disc(const double *A)
+{
+    static const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
+    double At[9] = {A[0], A[3], A[6], A[1], A[4], A[7], A[2], A[5], A[8]};
+    double d0 = A[0] - A[4], d1 = A[0] - A[8], d2 = A[4] - A[8];
+    double u[14], v[14];
+    alg_dx(A, d0, d1, d2, u);
+    alg_dx(At, d0, d1, d2, v);
+    double disc = 0.0;
+    for (int i = 0; i < 14; ++i)
+        disc = disc + w[i] * u[i] * v[i];
+    return disc;
+}
+
+/* ---------------------------------------------------------------- Alg. 9 */
+static void alg_eigvals(double I1, double J2, double J3, double disc, double *lam)
+{
+    const double pi = 3.14159265358979323846;
+    double phi = atan2(sqrt(27.0 * fmax(disc, 0.0)), 27.0 * J3);
+    double r = 2.0 * sqrt(3.0 * fmax(J2, 0.0));
+    for (int k = 1; k <= 3; ++k)
+        lam[k - 1] = (I1 + r * cos((phi + 2.0 * pi * k) / 3.0)) / 3.0;
+    /* ascending order */
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2 - i; ++j)
+            if (lam[j] > lam[j + 1]) {
+                double t = lam[j];
+                lam[j] = lam[j + 1];
+                lam[j + 1] = t;
+            }
+}
+
+static void one_eigvals(const double *A, double *lam)
+{
+    alg_eigvals(alg_I1(A), alg_J2(A), alg_J3(A), alg_disc(A), lam);
+}
+
+/* -------------------------------------------------- backward, E_k route */
+static void one_backward(const double *A, const double *g, double *grad)
+{
+    double lam[3];
+    one_eigvals(A, lam);
+    for (int e = 0; e < 9; ++e)
+        grad[e] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        int i = (k + 1) % 3, j = (k + 2) % 3;
+        double P[9], Q[9], E[9];
+        for (int e = 0; e < 9; ++e) {
+            P[e] = A[e];
+            Q[e] = A[e];
+        }
+        P[0] -= lam[i]; P[4] -= lam[i]; P[8] -= lam[i];
+        Q[0] -= lam[j]; Q[4] -= lam[j]; Q[8] -= lam[j];
+        double den = (lam[k] - lam[i]) * (lam[k] - lam[j]);
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                E[3 * r + c] = (P[3 * r + 0] * Q[0 + c] + P[3 * r + 1] * Q[3 + c] + P[3 * r + 2] * Q[6 + c]) / den;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                grad[3 * r + c] += g[k] * E[3 * c + r]; /* E_k^T */
+    }
+}
+
+/* ------------------------------------------------------------ exports */
+#define EXPORT __attribute__((visibility("default")))
+
+static void set_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
+EXPORT int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* I1, J2, J3, Delta of n row-major matrices a[n*9]; each output has n doubles */
+EXPORT void oracle_invariants(int64_t n, const double *a, double *i1, double *j2, double *j3,
+                              double *disc, int threads)
+{
+    set_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n; ++m) {
+        const double *A = a + 9 * m;
+        i1[m] = alg_I1(A);
+        j2[m] = alg_J2(A);
+        j3[m] = alg_J3(A);
+        disc[m] = alg_disc(A);
+    }
+}
+
+/* the auxiliary vectors u = dx(A), v = dx(A^T) of one matrix (14 each) */
+EXPORT void oracle_aux_vectors(const double *A, double *u, double *v)
+{
+    double At[9] = {A[0], A[3], A[6], A[1], A[4], A[7], A[2], A[5], A[8]};
+    double d0 = A[0] - A[4], d1 = A[0] - A[8], d2 = A[4] - A[8];
+    alg_dx(A, d0, d1, d2, u);
+    alg_dx(At, d0, d1, d2, v);
+}
+
+/* eigenvalues, ascending: lam[n*3] */
+EXPORT void oracle_eigvals(int64_t n, const double *a, double *lam, int threads)
+{
+    set_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n; ++m)
+        one_eigvals(a + 9 * m, lam + 3 * m);
+}
+
+/* eigenvalues from given invariants (Alg. 9 alone): lam[n*3] */
+EXPORT void oracle_eigvals_from_invariants(int64_t n, const double *i1, const double *j2,
+                                           const double *j3, const double *disc, double *lam)
+{
+    for (int64_t m = 0; m < n; ++m)
+        alg_eigvals(i1[m], j2[m], j3[m], disc[m], lam + 3 * m);
+}
+
+/* vector-Jacobian product: grad[n*9] = sum_k g[n*3]_k d(lambda_k)/dA */
+EXPORT void oracle_eigvals_backward(int64_t n, const double *a, const double *g, double *grad,
+                                    int threads)
+{
+    set_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n; ++m)
+        one_backward(a + 9 * m, g + 3 * m, grad + 9 * m);
+}
