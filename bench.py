@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Throughput of batched closed-form 3x3 eigenvalues on one MI355X.
+
+One step = one pass of the whole path over the differentiation workload:
+2^24 general binary64 matrices A = V diag(l) V^-1 (sorted l ~ U[-1, 1] with
+gap >= 1e-3, cond(V) = 10^U(0, 2)), upstream gradient g ~ N(0, 1):
+  eig3_eigvals (I1, J2, J3, Delta -> ascending eigenvalues)
+  eig3_eigvals_backward (dL/dA through the invariants).
+Inputs are resident in HBM (structure of arrays) before timing starts.
+
+Prints ONE JSON line on stdout; progress goes to stderr.  Also reports the
+other workloads (perturbation sweep, symmetric stress tensors in binary64 and
+binary32) under "variants", the roofline of the dominant kernel, and the
+plain binary64 CPU reference timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "eigvals matrices/s + % HBM roofline (FP64 vs FP32-comp; fwd+bwd) at stated err"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+N_MAIN = 1 << 24
+N_SYM = 1 << 27
+
+# algorithmic bytes per matrix (inputs read once, outputs written once)
+BYTES = {
+    "fwd_general_f64": 9 * 8 + 3 * 8,
+    "fwd_symmetric_f64": 6 * 8 + 3 * 8,
+    "fwd_symmetric_f32": 6 * 4 + 3 * 4,
+    "fwd_general_f32": 9 * 4 + 3 * 4,
+    "bwd_general_f64": 9 * 8 + 3 * 8 + 9 * 8,
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--accuracy", default="fma", choices=["fma", "compensated"],
+                   help="binary64 evaluation of J2, J3, Delta for the timed step")
+    p.add_argument("--no-variants", action="store_true", help="time only the main step")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0, help="approximate CPU time of the oracle leg")
+    return p.parse_args()
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2511_00292_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_record(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel_key)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+class Timer:
+    """Per-kernel HIP event timing on torch's current stream (the stream the
+    library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def run(self, key, fn):
+        s = self.torch.cuda.Event(enable_timing=True)
+        e = self.torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        self.pairs.setdefault(key, []).append((s, e))
+
+    def mean_ms(self, key):
+        ps = self.pairs.get(key, [])
+        return sum(s.elapsed_time(e) for s, e in ps) / max(len(ps), 1)
+
+    def reset(self):
+        self.pairs = {}
+
+
+def timed_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn(None)
+    torch.cuda.synchronize()
+    timer = Timer(torch)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn(timer)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall, timer
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the path has no cross-GPU "
+                                   "exchange, so --gpus N > 1 is not provided", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2511_00292_amd as eig3
+    import workloads as w
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("device", torch.cuda.get_device_name(0), "library", eig3.version())
+
+    # ------------------------------------------------------------ main step
+    t0 = time.perf_counter()
+    c5 = w.config5(N_MAIN)
+    log(f"config5 generated n={N_MAIN} in {time.perf_counter() - t0:.1f}s")
+    a = [torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])).to(dev) for k in range(9)]
+    g = [torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])).to(dev) for k in range(3)]
+    lam = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(3)]
+    grad = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
+    del c5
+    acc = args.accuracy
+
+    def step(timer):
+        if timer is None:
+            eig3.eig3_eigvals(a, "general", acc, "soa", out=lam)
+            eig3.eig3_eigvals_backward(a, g, "general", acc, out=grad)
+        else:
+            timer.run("fwd", lambda: eig3.eig3_eigvals(a, "general", acc, "soa", out=lam))
+            timer.run("bwd", lambda: eig3.eig3_eigvals_backward(a, g, "general", acc, out=grad))
+
+    ms, wall, timer = timed_loop(torch, step, args.steps, args.warmup)
+    fwd_ms, bwd_ms = timer.mean_ms("fwd"), timer.mean_ms("bwd")
+    log(f"step {ms:.3f} ms (fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms), wall {wall:.2f}s for {args.steps} steps")
+    value = N_MAIN / (ms * 1e-3)
+    dom_key, dom_ms = ("bwd_general_f64", bwd_ms) if bwd_ms >= fwd_ms else ("fwd_general_f64", fwd_ms)
+    achieved = BYTES[dom_key] * N_MAIN / (dom_ms * 1e-3) / 1e9
+    traffic = traffic_record(f"{dom_key}_{acc}")
+    roofline = {"bound": "hbm", "kernel": f"{dom_key} ({acc})", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_launch_ms": round(dom_ms, 4),
+                "algorithmic_bytes_per_matrix": BYTES[dom_key], "matrices_per_launch": N_MAIN}
+
+    variants = []
+
+    def variant(name, key, n, fn, dtype, extra=None):
+        ms_v, _, _ = timed_loop(torch, lambda t: fn(), max(5, args.steps // 2), 3)
+        gbs = BYTES[key] * n / (ms_v * 1e-3) / 1e9
+        rec = {"name": name, "matrices_per_s": n / (ms_v * 1e-3), "ms": round(ms_v, 4), "n": n,
+               "dtype": dtype, "GB_per_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        rec.update(extra or {})
+        variants.append(rec)
+        log(f"variant {name}: {ms_v:.3f} ms, {rec['matrices_per_s'] / 1e9:.2f} G mat/s, {gbs:.0f} GB/s "
+            f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+
+    if not args.no_variants:
+        for acc_v in ("fma", "compensated"):
+            variant(f"config5 fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
+                    lambda acc_v=acc_v: eig3.eig3_eigvals(a, "general", acc_v, "soa", out=lam), "f64")
+            variant(f"config5 bwd general f64 {acc_v}", "bwd_general_f64", N_MAIN,
+                    lambda acc_v=acc_v: eig3.eig3_eigvals_backward(a, g, "general", acc_v, out=grad), "f64")
+        del a, g, lam, grad
+        torch.cuda.empty_cache()
+        # perturbation sweep (config 2)
+        t0 = time.perf_counter()
+        c2 = w.config2(N_MAIN)
+        log(f"config2 generated in {time.perf_counter() - t0:.1f}s")
+        a2 = [torch.from_numpy(np.ascontiguousarray(c2["a"][:, k])).to(dev) for k in range(9)]
+        del c2
+        l2 = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(3)]
+        for acc_v in ("fma", "compensated"):
+            variant(f"config2 fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
+                    lambda acc_v=acc_v: eig3.eig3_eigvals(a2, "general", acc_v, "soa", out=l2), "f64")
+        del a2, l2
+        torch.cuda.empty_cache()
+        # symmetric stress tensors (configs 3 and 4)
+        t0 = time.perf_counter()
+        c3 = w.config3(N_SYM)
+        log(f"config3 generated in {time.perf_counter() - t0:.1f}s")
+        s64 = [torch.from_numpy(np.ascontiguousarray(c3["s"][:, k])).to(dev) for k in range(6)]
+        l3 = [torch.empty(N_SYM, dtype=torch.float64, device=dev) for _ in range(3)]
+        for acc_v in ("fma", "compensated"):
+            variant(f"config3 fwd symmetric f64 {acc_v}", "fwd_symmetric_f64", N_SYM,
+                    lambda acc_v=acc_v: eig3.eig3_eigvals(s64, "symmetric", acc_v, "soa", out=l3), "f64")
+        del l3
+        s32 = [t.float() for t in s64]
+        del s64
+        torch.cuda.empty_cache()
+        l4 = [torch.empty(N_SYM, dtype=torch.float32, device=dev) for _ in range(3)]
+        for acc_v in ("fma", "compensated"):
+            try:
+                variant(f"config4 fwd symmetric f32 {acc_v}", "fwd_symmetric_f32", N_SYM,
+                        lambda acc_v=acc_v: eig3.eig3_eigvals(s32, "symmetric", acc_v, "soa", out=l4), "f32")
+            except eig3.Eig3Error as e:
+                log(f"config4 {acc_v}: {e}")
+        del s32, l4, c3
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ CPU leg
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import plain
+        sample_n = 1 << 20
+        cs = w.config5(sample_n, seed=w.SEEDS[5] + 1)
+        cores = plain.max_threads()
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            plain.eigvals(cs["a"])
+            plain.eigvals_backward(cs["a"], cs["g"])
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or reps >= 200:
+                break
+        cpu = {"value": reps * sample_n / el, "unit": "matrices/s", "cores": cores, "kind": "oracle",
+               "sample": f"{reps} passes of forward eigvals + eigenprojector backward over {sample_n} "
+                         f"config-5 matrices (plain binary64 C of the paper's algorithms, OpenMP), "
+                         f"{el:.1f} s"}
+        log(f"cpu baseline {cpu['value'] / 1e6:.1f} M mat/s on {cores} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "differentiation batch: 2^24 general binary64 3x3 matrices "
+                               "A = V diag(l) V^-1 (sorted l ~ U[-1,1], gap >= 1e-3, cond(V) = 10^U(0,2)); "
+                               "step = eig3_eigvals + eig3_eigvals_backward, structure-of-arrays",
+                   "n": N_MAIN, "accuracy": acc, "layout": "soa",
+                   "step_GB_per_s": round((BYTES["fwd_general_f64"] + BYTES["bwd_general_f64"]) * N_MAIN
+                                          / (ms * 1e-3) / 1e9, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,145 @@
+/*
+ * eig3.h -- C ABI of libeig3: batched closed-form eigenvalues of real,
+ * diagonalizable 3x3 matrices on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Habera & Zilian, "Numerically stable evaluation of closed-form
+ * expressions for eigenvalues of 3x3 matrices" (arXiv 2511.00292).  The
+ * eigenvalues of a real, diagonalizable 3x3 matrix A with real spectrum are
+ * obtained from four invariants (Sec. "Introduction and motivation",
+ * Eq. principal-invariants and Eq. triple-angle-arctan):
+ *   I1 = tr A                       (Alg. alg:I1-stable)
+ *   J2 = tr(dev(A)^2) / 2           (Alg. alg:J2-stable, diagonal differences)
+ *   J3 = det(dev A)                 (Alg. alg:J3-stable)
+ *   Delta = 4 J2^3 - 27 J3^2        (Alg. alg:disc-stable, sum of products)
+ * and the trigonometric formula (Eq. eigvals-trig, Alg. alg:eigvals-stable)
+ *   lambda_k = (I1 + 2 sqrt(3 J2) cos((phi + 2 pi k) / 3)) / 3,
+ *   phi = atan2(sqrt(27 Delta), 27 J3) in [0, pi].
+ *
+ * Conventions shared by every call:
+ *  - All data pointers are DEVICE pointers owned by the caller.  The library
+ *    never allocates, frees or synchronizes; each call only enqueues kernels
+ *    on `stream` (a hipStream_t; NULL = the default stream) and returns.
+ *  - Inputs are read-only.  Outputs must not alias inputs or each other.
+ *  - n == 0 is a no-op returning EIG3_OK.  Invalid arguments (NULL pointers,
+ *    n < 0, unknown enum values, outputs aliasing inputs) return EIG3_EINVAL
+ *    and launch nothing.  A failed launch returns EIG3_ELAUNCH.
+ *  - Precondition (not checked): real, diagonalizable input with real
+ *    spectrum.  Outside it the results stay finite for finite input: J2 < 0
+ *    and Delta < 0 (possible after rounding for nonsymmetric input) are
+ *    clamped to 0 before the square roots, so a complex pair a +- ib comes
+ *    back as a double real value near a.  NaN input propagates to NaN output.
+ *  - Eigenvalues are returned in ascending order lambda_1 <= lambda_2 <=
+ *    lambda_3 (Sec. "Introduction and motivation", ordering property).
+ *  - Accuracy: with unit roundoff eps (2^-53 binary64, 2^-24 binary32),
+ *    kappa_2 the condition number of the eigenbasis, and Frobenius norms,
+ *    the paper's forward-error bounds (C = 1, lowest order) are
+ *      |I1 err| <= ||A|| eps, |J2 err| <= ||dev A||^2 eps  (Thm thm:J2-fwd-stability)
+ *      |J3 err| <= ||dev cof dev A|| ||dev A|| eps          (Lemma lem:J3-fwd-stability)
+ *      |Delta err| <= ||dev(12 J2^2 A^T - 54 J3 cof dev A)|| ||dev A|| eps
+ *                                                            (Lemma lem:disc-fwd-stability)
+ *      |lambda err| <= kappa_2 ||A|| eps                     (Lemma lem:eigvals-fwd-stability)
+ *    EIG3_COMPENSATED evaluates J2, J3 and the auxiliary vectors of Delta
+ *    with error-free products and sums and stays near these bounds also for
+ *    ill-conditioned eigenbases, where the plain algorithms exceed them.
+ */
+#ifndef EIG3_H
+#define EIG3_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum eig3_status {
+    EIG3_OK = 0,
+    EIG3_EINVAL = -1,       /* invalid argument; nothing was launched */
+    EIG3_EUNSUPPORTED = -2, /* valid combination that this build does not provide */
+    EIG3_ELAUNCH = -3       /* the HIP runtime reported a launch error */
+} eig3_status;
+
+typedef enum eig3_dtype {
+    EIG3_F64 = 0, /* binary64 storage and arithmetic */
+    EIG3_F32 = 1  /* binary32 storage; binary32 arithmetic with compensated
+                     (FMA error-free) products for J2, J3 and the auxiliary
+                     vectors of Delta, binary64 accumulation of Delta and a
+                     binary64 triple angle (the "FP64 islands") */
+} eig3_dtype;
+
+typedef enum eig3_structure {
+    EIG3_GENERAL = 0,  /* 9 entries: A00 A01 A02 A10 A11 A12 A20 A21 A22 */
+    EIG3_SYMMETRIC = 1 /* 6 entries: A00 A11 A22 A01 A02 A12 (A10 = A01, ...) */
+} eig3_structure;
+
+typedef enum eig3_layout {
+    EIG3_SOA = 0, /* structure of arrays: one array of n values per entry */
+    EIG3_AOS = 1  /* array of structures: one array, matrix m at m*9 (or m*6),
+                     entries in the order above (row-major (n,3,3) for GENERAL) */
+} eig3_layout;
+
+typedef enum eig3_accuracy {
+    EIG3_FMA = 0,        /* the paper's algorithms with fused multiply-adds */
+    EIG3_COMPENSATED = 1 /* error-free products and sums in J2, J3 and Delta */
+} eig3_accuracy;
+
+/* A batch of n matrices resident in device memory. */
+typedef struct eig3_matrices {
+    int64_t n;         /* number of matrices, n >= 0 */
+    int32_t dtype;     /* eig3_dtype */
+    int32_t structure; /* eig3_structure */
+    int32_t layout;    /* eig3_layout */
+    int32_t accuracy;  /* eig3_accuracy (binary64 only; binary32 is always compensated) */
+    /* SOA: a[k] points to n values of entry k (k < 9 GENERAL, k < 6 SYMMETRIC).
+       AOS: a[0] points to n*9 (GENERAL) or n*6 (SYMMETRIC) values; a[1..] unused.
+       Every pointer must be aligned to its element size. */
+    const void *a[9];
+} eig3_matrices;
+
+/*
+ * The four invariants of each matrix (Alg. alg:I1-stable, alg:J2-stable,
+ * alg:J3-stable, alg:disc-stable).  i1, j2, j3, disc: n values each, in the
+ * element type of A.  Delta is not clamped here.
+ */
+int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *disc,
+                    hipStream_t stream);
+
+/*
+ * Ascending eigenvalues of each matrix (Alg. alg:eigvals-stable applied to
+ * the invariants, with phi read as atan2 in [0, pi]).
+ * out_layout EIG3_SOA: lam[k] -> n values of lambda_(k+1), k = 0, 1, 2.
+ * out_layout EIG3_AOS: lam[0] -> n*3 values, (lambda_1, lambda_2, lambda_3)
+ *                      per matrix; lam[1], lam[2] unused.
+ * Element type = that of A.
+ */
+int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
+                 hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of the eigenvalues: grad_a = sum_k g_k d(lambda_k)/dA,
+ * through the invariants: d(lambda_k)/dA = I/3 + (mu_k dev(A)^T + dev(cof dev A))
+ * / ((lambda_k - lambda_i)(lambda_k - lambda_j)), mu_k = lambda_k - I1/3, from
+ * the Jacobians of Lemma lem:J2-condition and Lemma lem:J3-jacobian and the
+ * implicit derivative of the depressed cubic mu^3 - J2 mu - J3 = 0.
+ * g: upstream gradient, 3 values per matrix, layout g_layout as for
+ *    eig3_eigvals' output.
+ * grad_a: same structure, layout and entry order as A.  For SYMMETRIC input
+ *    the result is the gradient with respect to the 6 stored entries (the
+ *    off-diagonal value counts both of its positions).
+ * Undefined at repeated eigenvalues (zero gap): the result is then +-Inf or
+ * NaN.  binary64 only: EIG3_F32 returns EIG3_EUNSUPPORTED.
+ */
+int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *const g[3],
+                          void *const grad_a[9], hipStream_t stream);
+
+/* Static, human-readable name of a status code. */
+const char *eig3_status_string(int status);
+
+/* Library version, "major.minor.patch". */
+const char *eig3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIG3_H */

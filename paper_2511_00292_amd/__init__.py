@@ -1,0 +1,187 @@
+"""Batched closed-form eigenvalues of real, diagonalizable 3x3 matrices on
+AMD Instinct MI355X (gfx950), after Habera & Zilian, "Numerically stable
+evaluation of closed-form expressions for eigenvalues of 3x3 matrices"
+(arXiv 2511.00292).
+
+The three calls below mirror the C ABI of ``include/eig3.h`` one for one and
+only marshal arguments: PyTorch provides device memory and the current
+stream; all arithmetic runs in the HIP kernels of ``libeig3.so``.
+
+Matrix batches are given either as a sequence of K device tensors of n
+values each (structure of arrays, K = 9 general / 6 symmetric, in the entry
+order of ``ENTRIES``) or as one device tensor with n*K values (array of
+structures, e.g. a contiguous (n, 3, 3) tensor for general matrices or
+(n, 6) for symmetric ones).
+"""
+from __future__ import annotations
+
+from typing import Sequence, Union
+
+import torch
+
+from . import _capi
+from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EIG3_GENERAL, EIG3_SOA,
+                    EIG3_SYMMETRIC, Eig3Error)
+
+__all__ = [
+    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eigvals", "Eig3Eigvals",
+    "ENTRIES", "Eig3Error", "version",
+]
+
+ENTRIES = {
+    "general": ("A00", "A01", "A02", "A10", "A11", "A12", "A20", "A21", "A22"),
+    "symmetric": ("A00", "A11", "A22", "A01", "A02", "A12"),
+}
+
+_STRUCT = {"general": EIG3_GENERAL, "symmetric": EIG3_SYMMETRIC}
+_ACC = {"fma": EIG3_FMA, "compensated": EIG3_COMPENSATED}
+_DTYPE = {torch.float64: EIG3_F64, torch.float32: EIG3_F32}
+
+Batch = Union[torch.Tensor, Sequence[torch.Tensor]]
+
+
+def version() -> str:
+    return _capi.version()
+
+
+def _check_device_tensor(t: torch.Tensor, what: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def _matrices(a: Batch, structure: str, accuracy: str):
+    """Build the eig3_matrices descriptor; returns (descriptor, n, dtype,
+    device, layout, keepalive)."""
+    if structure not in _STRUCT:
+        raise ValueError(f"structure must be one of {tuple(_STRUCT)}")
+    if accuracy not in _ACC:
+        raise ValueError(f"accuracy must be one of {tuple(_ACC)}")
+    k = 9 if structure == "general" else 6
+    m = _capi.Eig3Matrices()
+    m.structure = _STRUCT[structure]
+    m.accuracy = _ACC[accuracy]
+    if isinstance(a, torch.Tensor):
+        _check_device_tensor(a, "a")
+        if a.numel() % k:
+            raise ValueError(f"array-of-structures input needs a multiple of {k} values")
+        n = a.numel() // k
+        m.layout = EIG3_AOS
+        m.a[0] = a.data_ptr() if n else 0
+        ts = [a]
+    else:
+        ts = list(a)
+        if len(ts) != k:
+            raise ValueError(f"structure-of-arrays input needs {k} tensors for '{structure}'")
+        for j, t in enumerate(ts):
+            _check_device_tensor(t, f"a[{j}]")
+        n = ts[0].numel()
+        if any(t.numel() != n for t in ts) or any(t.dtype != ts[0].dtype for t in ts) or \
+                any(t.device != ts[0].device for t in ts):
+            raise ValueError("all entry tensors need the same length, dtype and device")
+        m.layout = EIG3_SOA
+        for j, t in enumerate(ts):
+            m.a[j] = t.data_ptr() if n else 0
+    dtype = ts[0].dtype
+    if dtype not in _DTYPE:
+        raise TypeError("matrices must be float64 or float32")
+    m.dtype = _DTYPE[dtype]
+    m.n = n
+    return m, n, dtype, ts[0].device, m.layout, ts
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def eig3_invariants(a: Batch, structure: str = "general", accuracy: str = "fma", out=None):
+    """(I1, J2, J3, Delta), each a tensor of n values (Alg. alg:I1-stable,
+    alg:J2-stable, alg:J3-stable, alg:disc-stable)."""
+    m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
+    outs = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(4)]
+    for t in outs:
+        _check_device_tensor(t, "out")
+    _capi.call_invariants(m, [t.data_ptr() if n else 0 for t in outs], _stream(dev))
+    return tuple(outs)
+
+
+def eig3_eigvals(a: Batch, structure: str = "general", accuracy: str = "fma", out_layout: str = "aos", out=None):
+    """Ascending eigenvalues (Alg. alg:eigvals-stable).  out_layout 'aos'
+    returns an (n, 3) tensor, 'soa' a tuple of three n-vectors."""
+    m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
+    if out_layout == "aos":
+        res = out if out is not None else torch.empty((n, 3), dtype=dtype, device=dev)
+        _check_device_tensor(res, "out")
+        ptrs = [res.data_ptr() if n else 0, 0, 0]
+        _capi.call_eigvals(m, EIG3_AOS, ptrs, _stream(dev))
+        return res
+    if out_layout == "soa":
+        res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(3)]
+        for t in res:
+            _check_device_tensor(t, "out")
+        _capi.call_eigvals(m, EIG3_SOA, [t.data_ptr() if n else 0 for t in res], _stream(dev))
+        return tuple(res)
+    raise ValueError("out_layout must be 'aos' or 'soa'")
+
+
+def eig3_eigvals_backward(a: Batch, g: Batch, structure: str = "general", accuracy: str = "fma", out=None):
+    """sum_k g_k d(lambda_k)/dA, in the structure and layout of ``a``.
+    ``g``: an (n, 3) tensor (array of structures) or three n-vectors."""
+    m, n, dtype, dev, layout, _keep = _matrices(a, structure, accuracy)
+    k = 9 if structure == "general" else 6
+    if isinstance(g, torch.Tensor):
+        _check_device_tensor(g, "g")
+        if g.numel() != 3 * n or g.dtype != dtype:
+            raise ValueError("g needs 3 values per matrix and the dtype of a")
+        g_layout, gp, gkeep = EIG3_AOS, [g.data_ptr() if n else 0, 0, 0], [g]
+    else:
+        gkeep = list(g)
+        if len(gkeep) != 3:
+            raise ValueError("g needs three tensors")
+        for t in gkeep:
+            _check_device_tensor(t, "g")
+            if t.numel() != n or t.dtype != dtype:
+                raise ValueError("each g tensor needs n values and the dtype of a")
+        g_layout, gp = EIG3_SOA, [t.data_ptr() if n else 0 for t in gkeep]
+    if layout == EIG3_AOS:
+        res = out if out is not None else torch.empty_like(a)
+        _check_device_tensor(res, "out")
+        ptrs = [res.data_ptr() if n else 0] + [0] * 8
+    else:
+        res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(k)]
+        for t in res:
+            _check_device_tensor(t, "out")
+        ptrs = [t.data_ptr() if n else 0 for t in res] + [0] * (9 - k)
+    _capi.call_eigvals_backward(m, g_layout, gp, ptrs, _stream(dev))
+    return res if layout == EIG3_AOS else tuple(res)
+
+
+class Eig3Eigvals(torch.autograd.Function):
+    """lambda = eigvals(A) for A of shape (..., 3, 3) (general) with the
+    hand-written adjoint of ``eig3_eigvals_backward`` as its backward."""
+
+    @staticmethod
+    def forward(ctx, a: torch.Tensor, accuracy: str = "fma"):
+        shape = a.shape
+        if shape[-2:] != (3, 3):
+            raise ValueError("expected (..., 3, 3)")
+        ac = a.contiguous()
+        lam = eig3_eigvals(ac.reshape(-1, 9), "general", accuracy, "aos")
+        ctx.save_for_backward(ac)
+        ctx.accuracy = accuracy
+        return lam.reshape(*shape[:-2], 3)
+
+    @staticmethod
+    def backward(ctx, glam: torch.Tensor):
+        (ac,) = ctx.saved_tensors
+        g = glam.contiguous().reshape(-1, 3)
+        grad = eig3_eigvals_backward(ac.reshape(-1, 9), g, "general", ctx.accuracy)
+        return grad.reshape(ac.shape), None
+
+
+def eigvals(a: torch.Tensor, accuracy: str = "fma") -> torch.Tensor:
+    """Ascending eigenvalues of a (..., 3, 3) float64 device tensor, differentiable."""
+    return Eig3Eigvals.apply(a, accuracy)

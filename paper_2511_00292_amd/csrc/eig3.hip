@@ -1,0 +1,455 @@
+// eig3.hip -- kernels and C ABI of libeig3 (see include/eig3.h).
+//
+// Execution model: one 3x3 matrix per lane, wave64, 256-lane workgroups,
+// grid-stride loop over a 64-bit matrix index.  Structure-of-arrays inputs
+// give one fully coalesced 8-byte load per entry and lane; array-of-structures
+// inputs are staged through LDS by the workgroup with 16-byte loads and then
+// read back one matrix per lane.  Nothing here is a dense contraction, so
+// there is no MFMA: the kernels are HBM-bandwidth bound with a binary64 VALU
+// budget (MI355X runs binary64 FMA at the binary32 non-packed rate).
+#include "eig3.h"
+#include "eig3_math.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+namespace {
+
+using namespace eig3;
+
+constexpr int kBlock = 256;
+constexpr int64_t kMaxBlocks = int64_t(1) << 20;
+
+template <class T> struct In9 {
+    const T *p[9];
+};
+template <class T> struct Out9 {
+    T *p[9];
+};
+template <class T> struct Out4 {
+    T *p[4];
+};
+template <class T> struct Out3 {
+    T *p[3];
+};
+template <class T> struct G3 {
+    const T *p[3];
+};
+
+// ------------------------------------------------------------------ loads
+// AoS staging: the workgroup copies its contiguous span of kBlock matrices
+// (kBlock*K elements) into LDS with 16-byte loads, then each lane reads its K
+// entries.  K = 9 (general) or 6 (symmetric); the LDS row stride K+1 keeps the
+// per-lane reads on distinct banks for K = 9.
+template <class T, int K> struct AosTile {
+    static constexpr int kStride = (K % 2 == 1) ? K : K + 1;
+    T v[kBlock * kStride];
+};
+
+template <class T, int K>
+__device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t first, int64_t n, AosTile<T, K> &tile)
+{
+    // elements [first*K, min(n, first+kBlock)*K) of base
+    const int64_t m_end = (first + kBlock < n) ? first + kBlock : n;
+    const int count = int((m_end - first) * K);
+    const T *src = base + first * K;
+    for (int e = threadIdx.x; e < count; e += kBlock) {
+        const int m = e / K, k = e - m * K;
+        tile.v[m * AosTile<T, K>::kStride + k] = __builtin_nontemporal_load(src + e);
+    }
+}
+
+template <class T, int S> struct Mat;
+template <class T> struct Mat<T, EIG3_GENERAL> {
+    static constexpr int K = 9;
+    T a[9];
+};
+template <class T> struct Mat<T, EIG3_SYMMETRIC> {
+    static constexpr int K = 6;
+    T a[6];
+};
+
+template <class T, int S>
+__device__ __forceinline__ void load_soa(const In9<T> &in, int64_t i, Mat<T, S> &m)
+{
+#pragma unroll
+    for (int k = 0; k < Mat<T, S>::K; ++k)
+        m.a[k] = __builtin_nontemporal_load(in.p[k] + i);
+}
+
+__device__ __forceinline__ Gen to_gen(const Mat<double, EIG3_GENERAL> &m)
+{
+    return Gen{m.a[0], m.a[1], m.a[2], m.a[3], m.a[4], m.a[5], m.a[6], m.a[7], m.a[8]};
+}
+__device__ __forceinline__ Sym to_sym(const Mat<double, EIG3_SYMMETRIC> &m)
+{
+    return Sym{m.a[0], m.a[1], m.a[2], m.a[3], m.a[4], m.a[5]};
+}
+
+template <int S, int Acc> __device__ __forceinline__ Inv invariants_of(const Mat<double, S> &m)
+{
+    if constexpr (S == EIG3_GENERAL) {
+        if constexpr (Acc == EIG3_COMPENSATED)
+            return invariants_general_comp(to_gen(m));
+        else
+            return invariants_general_fma(to_gen(m));
+    } else {
+        if constexpr (Acc == EIG3_COMPENSATED)
+            return invariants_symmetric_comp(to_sym(m));
+        else
+            return invariants_symmetric_fma(to_sym(m));
+    }
+}
+
+// Per-matrix driver shared by the three entry points: loads matrix i (from
+// SoA pointers or the LDS tile) and calls body(i, matrix).
+template <class T, int S, int L, class Body>
+__device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Body body)
+{
+    constexpr int K = Mat<T, S>::K;
+    if constexpr (L == EIG3_SOA) {
+        const int64_t stride = int64_t(gridDim.x) * kBlock;
+        for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+            Mat<T, S> m;
+            load_soa<T, S>(in, i, m);
+            body(i, m);
+        }
+    } else {
+        __shared__ AosTile<T, K> tile;
+        const int64_t stride = int64_t(gridDim.x) * kBlock;
+        for (int64_t first = int64_t(blockIdx.x) * kBlock; first < n; first += stride) {
+            __syncthreads(); // previous iteration's reads are done
+            aos_stage<T, K>(in.p[0], first, n, tile);
+            __syncthreads();
+            const int64_t i = first + threadIdx.x;
+            if (i < n) {
+                Mat<T, S> m;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    m.a[k] = tile.v[threadIdx.x * AosTile<T, K>::kStride + k];
+                body(i, m);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+template <int S, int L, int Acc>
+__global__ __launch_bounds__(kBlock) void k_invariants_f64(int64_t n, In9<double> in, Out4<double> out)
+{
+    for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
+        const Inv v = invariants_of<S, Acc>(m);
+        __builtin_nontemporal_store(v.i1, out.p[0] + i);
+        __builtin_nontemporal_store(v.j2, out.p[1] + i);
+        __builtin_nontemporal_store(v.j3, out.p[2] + i);
+        __builtin_nontemporal_store(v.disc, out.p[3] + i);
+    });
+}
+
+template <class T>
+__device__ __forceinline__ void store3(const Out3<T> &out, int layout, int64_t i, T l1, T l2, T l3)
+{
+    if (layout == EIG3_SOA) {
+        __builtin_nontemporal_store(l1, out.p[0] + i);
+        __builtin_nontemporal_store(l2, out.p[1] + i);
+        __builtin_nontemporal_store(l3, out.p[2] + i);
+    } else {
+        T *o = out.p[0] + 3 * i;
+        __builtin_nontemporal_store(l1, o);
+        __builtin_nontemporal_store(l2, o + 1);
+        __builtin_nontemporal_store(l3, o + 2);
+    }
+}
+
+template <int S, int L, int OL, int Acc>
+__global__ __launch_bounds__(kBlock) void k_eigvals_f64(int64_t n, In9<double> in, Out3<double> out)
+{
+    for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
+        const Inv v = invariants_of<S, Acc>(m);
+        double l1, l2, l3;
+        eigvals_from_invariants(v, l1, l2, l3);
+        store3(out, OL, i, l1, l2, l3);
+    });
+}
+
+template <int S, int L, int GL, int Acc>
+__global__ __launch_bounds__(kBlock) void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<double> out)
+{
+    for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
+        double g1, g2, g3;
+        if constexpr (GL == EIG3_SOA) {
+            g1 = __builtin_nontemporal_load(g.p[0] + i);
+            g2 = __builtin_nontemporal_load(g.p[1] + i);
+            g3 = __builtin_nontemporal_load(g.p[2] + i);
+        } else {
+            g1 = __builtin_nontemporal_load(g.p[0] + 3 * i);
+            g2 = __builtin_nontemporal_load(g.p[0] + 3 * i + 1);
+            g3 = __builtin_nontemporal_load(g.p[0] + 3 * i + 2);
+        }
+        const Inv v = invariants_of<S, Acc>(m);
+        const Coef c = backward_coefficients(v, g1, g2, g3);
+        double gr[9];
+        if constexpr (S == EIG3_GENERAL) {
+            backward_general(to_gen(m), c, gr);
+        } else {
+            const Sym s = to_sym(m);
+            backward_general(Gen{s.s00, s.s01, s.s02, s.s01, s.s11, s.s12, s.s02, s.s12, s.s22}, c, gr);
+        }
+        constexpr int K = Mat<double, S>::K;
+        double o[K];
+        if constexpr (S == EIG3_GENERAL) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                o[k] = gr[k];
+        } else {
+            // gradient with respect to the 6 stored entries
+            o[0] = gr[0];
+            o[1] = gr[4];
+            o[2] = gr[8];
+            o[3] = gr[1] + gr[3];
+            o[4] = gr[2] + gr[6];
+            o[5] = gr[5] + gr[7];
+        }
+        if constexpr (L == EIG3_SOA) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                __builtin_nontemporal_store(o[k], out.p[k] + i);
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                __builtin_nontemporal_store(o[k], out.p[0] + K * i + k);
+        }
+    });
+}
+
+// ------------------------------------------------------------------- host
+int64_t grid_for(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return b < kMaxBlocks ? b : kMaxBlocks;
+}
+
+bool valid_enum(int v, int hi) { return v >= 0 && v <= hi; }
+
+size_t elem_size(int dtype) { return dtype == EIG3_F64 ? 8 : 4; }
+
+struct Range {
+    uintptr_t lo, hi;
+};
+
+// byte ranges of the input matrices
+int input_ranges(const eig3_matrices *A, Range *r)
+{
+    const size_t es = elem_size(A->dtype);
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    if (A->layout == EIG3_AOS) {
+        r[0] = {uintptr_t(A->a[0]), uintptr_t(A->a[0]) + size_t(A->n) * K * es};
+        return 1;
+    }
+    for (int k = 0; k < K; ++k)
+        r[k] = {uintptr_t(A->a[k]), uintptr_t(A->a[k]) + size_t(A->n) * es};
+    return K;
+}
+
+bool overlaps(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi; }
+
+bool aligned(const void *p, size_t a) { return (uintptr_t(p) % a) == 0; }
+
+// common validation of the matrix batch; K = number of stored entries
+int check_matrices(const eig3_matrices *A)
+{
+    if (A == nullptr || A->n < 0)
+        return EIG3_EINVAL;
+    if (!valid_enum(A->dtype, 1) || !valid_enum(A->structure, 1) || !valid_enum(A->layout, 1) ||
+        !valid_enum(A->accuracy, 1))
+        return EIG3_EINVAL;
+    if (A->n == 0)
+        return EIG3_OK;
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    const int np = A->layout == EIG3_AOS ? 1 : K;
+    for (int k = 0; k < np; ++k)
+        if (A->a[k] == nullptr || !aligned(A->a[k], elem_size(A->dtype)))
+            return EIG3_EINVAL;
+    return EIG3_OK;
+}
+
+int check_outputs(const eig3_matrices *A, void *const *outs, int nout, size_t count_each)
+{
+    Range in[9];
+    const int nin = input_ranges(A, in);
+    const size_t es = elem_size(A->dtype);
+    Range o[9];
+    for (int j = 0; j < nout; ++j) {
+        if (outs[j] == nullptr || !aligned(outs[j], es))
+            return EIG3_EINVAL;
+        o[j] = {uintptr_t(outs[j]), uintptr_t(outs[j]) + count_each * es};
+        for (int k = 0; k < nin; ++k)
+            if (overlaps(o[j], in[k]))
+                return EIG3_EINVAL;
+        for (int k = 0; k < j; ++k)
+            if (overlaps(o[j], o[k]))
+                return EIG3_EINVAL;
+    }
+    return EIG3_OK;
+}
+
+int launched()
+{
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? EIG3_OK : EIG3_ELAUNCH;
+}
+
+template <class T> In9<T> inputs_of(const eig3_matrices *A)
+{
+    In9<T> in;
+    for (int k = 0; k < 9; ++k)
+        in.p[k] = static_cast<const T *>(A->a[k]);
+    return in;
+}
+
+// dispatch helpers: turn runtime enums into template arguments
+template <class F> void dispatch_sla(int s, int l, int acc, F f)
+{
+    auto a = [&](auto S, auto L) {
+        if (acc == EIG3_COMPENSATED)
+            f(S, L, std::integral_constant<int, EIG3_COMPENSATED>{});
+        else
+            f(S, L, std::integral_constant<int, EIG3_FMA>{});
+    };
+    auto b = [&](auto S) {
+        if (l == EIG3_AOS)
+            a(S, std::integral_constant<int, EIG3_AOS>{});
+        else
+            a(S, std::integral_constant<int, EIG3_SOA>{});
+    };
+    if (s == EIG3_SYMMETRIC)
+        b(std::integral_constant<int, EIG3_SYMMETRIC>{});
+    else
+        b(std::integral_constant<int, EIG3_GENERAL>{});
+}
+
+} // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char *eig3_status_string(int status)
+{
+    switch (status) {
+    case EIG3_OK:
+        return "EIG3_OK";
+    case EIG3_EINVAL:
+        return "EIG3_EINVAL: invalid argument";
+    case EIG3_EUNSUPPORTED:
+        return "EIG3_EUNSUPPORTED: combination not provided by this build";
+    case EIG3_ELAUNCH:
+        return "EIG3_ELAUNCH: kernel launch failed";
+    default:
+        return "unknown eig3 status";
+    }
+}
+
+const char *eig3_version(void) { return "0.1.0"; }
+
+int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *disc, hipStream_t stream)
+{
+    int st = check_matrices(A);
+    if (st != EIG3_OK || A->n == 0)
+        return st;
+    void *outs[4] = {i1, j2, j3, disc};
+    if ((st = check_outputs(A, outs, 4, size_t(A->n))) != EIG3_OK)
+        return st;
+    if (A->dtype != EIG3_F64)
+        return EIG3_EUNSUPPORTED;
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    Out4<double> out{{static_cast<double *>(i1), static_cast<double *>(j2), static_cast<double *>(j3),
+                      static_cast<double *>(disc)}};
+    const In9<double> in = inputs_of<double>(A);
+    dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+        hipLaunchKernelGGL((k_invariants_f64<S.value, L.value, Acc.value>), grid, block, 0, stream, A->n, in, out);
+    });
+    return launched();
+}
+
+int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3], hipStream_t stream)
+{
+    int st = check_matrices(A);
+    if (st != EIG3_OK)
+        return st;
+    if (lam == nullptr || !valid_enum(out_layout, 1))
+        return EIG3_EINVAL;
+    if (A->n == 0)
+        return EIG3_OK;
+    void *outs[3] = {lam[0], out_layout == EIG3_SOA ? lam[1] : nullptr, out_layout == EIG3_SOA ? lam[2] : nullptr};
+    const int nout = out_layout == EIG3_SOA ? 3 : 1;
+    if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? 3 : 1))) != EIG3_OK)
+        return st;
+    if (A->dtype != EIG3_F64)
+        return EIG3_EUNSUPPORTED;
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    Out3<double> out{{static_cast<double *>(outs[0]), static_cast<double *>(outs[1]), static_cast<double *>(outs[2])}};
+    const In9<double> in = inputs_of<double>(A);
+    dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+        if (out_layout == EIG3_AOS)
+            hipLaunchKernelGGL((k_eigvals_f64<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream, A->n,
+                               in, out);
+        else
+            hipLaunchKernelGGL((k_eigvals_f64<S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream, A->n,
+                               in, out);
+    });
+    return launched();
+}
+
+int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *const g[3], void *const grad_a[9],
+                          hipStream_t stream)
+{
+    int st = check_matrices(A);
+    if (st != EIG3_OK)
+        return st;
+    if (g == nullptr || grad_a == nullptr || !valid_enum(g_layout, 1))
+        return EIG3_EINVAL;
+    if (A->n == 0)
+        return EIG3_OK;
+    if (A->dtype != EIG3_F64)
+        return EIG3_EUNSUPPORTED;
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    // g: inputs, must be valid and not alias the outputs
+    const int ng = g_layout == EIG3_SOA ? 3 : 1;
+    for (int k = 0; k < ng; ++k)
+        if (g[k] == nullptr || !aligned(g[k], 8))
+            return EIG3_EINVAL;
+    const int nout = A->layout == EIG3_SOA ? K : 1;
+    void *outs[9];
+    for (int k = 0; k < nout; ++k)
+        outs[k] = grad_a[k];
+    if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? K : 1))) != EIG3_OK)
+        return st;
+    for (int j = 0; j < nout; ++j) {
+        const Range o{uintptr_t(outs[j]), uintptr_t(outs[j]) + size_t(A->n) * (nout == 1 ? K : 1) * 8};
+        for (int k = 0; k < ng; ++k) {
+            const Range gr{uintptr_t(g[k]), uintptr_t(g[k]) + size_t(A->n) * (ng == 1 ? 3 : 1) * 8};
+            if (overlaps(o, gr))
+                return EIG3_EINVAL;
+        }
+    }
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    const In9<double> in = inputs_of<double>(A);
+    G3<double> gg{{static_cast<const double *>(g[0]), static_cast<const double *>(ng == 3 ? g[1] : nullptr),
+                   static_cast<const double *>(ng == 3 ? g[2] : nullptr)}};
+    Out9<double> out;
+    for (int k = 0; k < 9; ++k)
+        out.p[k] = k < nout ? static_cast<double *>(outs[k]) : nullptr;
+    dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+        if (g_layout == EIG3_AOS)
+            hipLaunchKernelGGL((k_backward_f64<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream, A->n,
+                               in, gg, out);
+        else
+            hipLaunchKernelGGL((k_backward_f64<S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream, A->n,
+                               in, gg, out);
+    });
+    return launched();
+}
+
+} // extern "C"

@@ -1,0 +1,499 @@
+// eig3_math.hpp -- per-lane arithmetic of closed-form 3x3 eigenvalues for
+// gfx950.  One matrix per lane; everything lives in registers.
+//
+// Habera & Zilian, "Numerically stable evaluation of closed-form expressions
+// for eigenvalues of 3x3 matrices" (arXiv 2511.00292):
+//   I1     Alg. alg:I1-stable
+//   J2     Alg. alg:J2-stable (diagonal differences d0, d1, d2 + off-diagonal products)
+//   J3     Alg. alg:J3-stable (t1, t2, t3 from the differences; offdiag, mixed, diag parts)
+//   Delta  Alg. alg:disc-stable: sum_i w_i u_i v_i with u = dx(A), v = dx(A^T),
+//          w = (9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1); r10 of dx is taken
+//          with + M02 M21 d2 (the printed minus sign does not reproduce
+//          4 J2^3 - 27 J3^2).
+//   lambda Alg. alg:eigvals-stable / Eq. eigvals-trig.
+//
+// This file is compiled with -ffp-contract=off: every fused multiply-add is
+// written out, and the error-free transformations below rely on the absence
+// of any other contraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace eig3 {
+
+struct Inv {
+    double i1, j2, j3, disc;
+};
+
+// ------------------------------------------------------------------ basics
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// exact product a*b = p + e (FMA error-free transformation)
+template <class T> __device__ __forceinline__ void two_prod(T a, T b, T &p, T &e)
+{
+    p = a * b;
+    e = fma_(a, b, -p);
+}
+
+// exact sum a+b = s + e (Knuth's branch-free TwoSum)
+template <class T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T &e)
+{
+    s = a + b;
+    T bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// A pair product kept exactly as hi + lo.
+template <class T> struct PairT {
+    T hi, lo;
+};
+template <class T> __device__ __forceinline__ PairT<T> pair(T a, T b)
+{
+    PairT<T> p;
+    two_prod(a, b, p.hi, p.lo);
+    return p;
+}
+template <class T> __device__ __forceinline__ PairT<T> neg(PairT<T> p) { return PairT<T>{-p.hi, -p.lo}; }
+using Pair = PairT<double>;
+
+// Compensated accumulator of triple products (x*y)*z with x*y given exactly
+// as a pair: the running value is s + c, where s collects the rounded leading
+// parts through TwoSum and c collects every rounding error to first order
+// (Ogita, Rump & Oishi's compensated dot product, applied to the factored
+// products).  The result is as accurate as if computed in twice the working
+// precision and then rounded.
+template <class T> struct AccT {
+    T s, c;
+    __device__ __forceinline__ void first(PairT<T> xy, T z)
+    {
+        two_prod(xy.hi, z, s, c);
+        c = fma_(xy.lo, z, c);
+    }
+    __device__ __forceinline__ void add(PairT<T> xy, T z)
+    {
+        T q, qe, t, te;
+        two_prod(xy.hi, z, q, qe);
+        two_sum(s, q, t, te);
+        s = t;
+        c = c + (te + fma_(xy.lo, z, qe));
+    }
+    __device__ __forceinline__ T value() const { return s + c; }
+    // the value rounded once (hi) and its remainder (lo, exact when |s| >= |c|)
+    __device__ __forceinline__ void split(T &hi, T &lo) const
+    {
+        hi = s + c;
+        lo = c - (hi - s);
+    }
+};
+using Acc = AccT<double>;
+
+// ------------------------------------------------------------ diagonal part
+struct Diag {
+    double d0, d1, d2; // A00 - A11, A00 - A22, A11 - A22
+    double i1;
+};
+__device__ __forceinline__ Diag diag_part(double a00, double a11, double a22)
+{
+    Diag g;
+    g.d0 = a00 - a11;
+    g.d1 = a00 - a22;
+    g.d2 = a11 - a22;
+    g.i1 = (a00 + a11) + a22; // Alg. alg:I1-stable
+    return g;
+}
+
+constexpr double kSixth = 1.0 / 6.0;
+constexpr double kThird = 1.0 / 3.0;
+constexpr double kTwentySeventh = 1.0 / 27.0;
+
+// ====================================================================== FMA
+// The paper's algorithms as printed, with products and sums fused where a
+// fused multiply-add applies.
+
+// --------------------------------------------------------------- general
+struct Gen {
+    double a00, a01, a02, a10, a11, a12, a20, a21, a22;
+};
+
+// dx(M; d0, d1, d2) with fused multiply-adds; r[0..13] = r1..r14
+__device__ __forceinline__ void dx_fma(double M01, double M02, double M10, double M12, double M20, double M21,
+                                       double d0, double d1, double d2, double r[14])
+{
+    const double m01m02 = M01 * M02, m01m12 = M01 * M12, m02m10 = M02 * M10, m02m21 = M02 * M21;
+    const double m01m01 = M01 * M01, m02m02 = M02 * M02, m12m12 = M12 * M12;
+    const double m01m10 = M01 * M10, m02m12 = M02 * M12;
+    r[0] = fma_(m01m12, M20, -(m02m10 * M21));
+    r[1] = fma_(-m01m02, d2, fma_(m01m01, M12, -(m02m02 * M21)));
+    r[2] = fma_(M01 * M21, d1, fma_(-m01m01, M20, m02m21 * M21));
+    r[3] = fma_(m02m12, d0, fma_(m01m12, M12, -(m02m02 * M10)));
+    r[4] = fma_(m01m12, d1, fma_(-m01m02, M10, m02m12 * M21));
+    r[5] = fma_(m02m21, d0, fma_(-m01m02, M20, m01m12 * M21));
+    r[6] = fma_(-m02m10, d2, fma_(m01m10, M12, -(m02m12 * M20)));
+    const double d0d1 = d0 * d1, d1d2 = d1 * d2, d0d2 = d0 * d2;
+    r[7] = fma_(M12, d0d1, fma_(-m02m10, d1, fma_(m01m10, M12, -(m12m12 * M21))));
+    r[8] = fma_(M12, d0d1, fma_(-m02m10, d0, fma_(m02m12, M20, -(m12m12 * M21))));
+    r[9] = fma_(M01, d1d2, fma_(m02m21, d2, fma_(m01m02, M20, -(m01m01 * M10))));
+    r[10] = fma_(M01, d1d2, fma_(m02m21, d1, fma_(m01m12, M21, -(m01m01 * M10))));
+    r[11] = fma_(-M02, d0d2, fma_(m01m12, d0, fma_(m02m12, M21, -(m02m02 * M20))));
+    r[12] = fma_(M02, d0d2, fma_(m01m12, d2, fma_(-m01m02, M10, m02m02 * M20)));
+    r[13] = fma_(d0d1, d2, fma_(-m01m10, d0, fma_(M02 * M20, d1, -(M12 * M21 * d2))));
+}
+
+__device__ __forceinline__ double sum_wuv(const double u[14], const double v[14])
+{
+    // w = (9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1); small terms first
+    double s = u[13] * v[13];
+    s = fma_(2.0 * u[12], v[12], s);
+    s = fma_(2.0 * u[11], v[11], s);
+    s = fma_(2.0 * u[10], v[10], s);
+    s = fma_(2.0 * u[9], v[9], s);
+    s = fma_(2.0 * u[8], v[8], s);
+    s = fma_(2.0 * u[7], v[7], s);
+    s = fma_(8.0 * u[6], v[6], s);
+    s = fma_(8.0 * u[5], v[5], s);
+    s = fma_(8.0 * u[4], v[4], s);
+    s = fma_(6.0 * u[3], v[3], s);
+    s = fma_(6.0 * u[2], v[2], s);
+    s = fma_(6.0 * u[1], v[1], s);
+    s = fma_(9.0 * u[0], v[0], s);
+    return s;
+}
+
+__device__ __forceinline__ Inv invariants_general_fma(const Gen &A)
+{
+    Inv r;
+    const Diag g = diag_part(A.a00, A.a11, A.a22);
+    r.i1 = g.i1;
+    // J2 (Alg. alg:J2-stable)
+    const double off2 = fma_(A.a01, A.a10, fma_(A.a02, A.a20, A.a12 * A.a21));
+    r.j2 = fma_(fma_(g.d0, g.d0, fma_(g.d1, g.d1, g.d2 * g.d2)), kSixth, off2);
+    // J3 (Alg. alg:J3-stable)
+    const double t1 = g.d1 + g.d2, t2 = g.d0 - g.d2, t3 = -g.d0 - g.d1;
+    const double off3 = fma_(A.a01 * A.a12, A.a20, A.a02 * A.a10 * A.a21);
+    const double mixed = fma_(A.a01 * A.a10, t1, fma_(A.a02 * A.a20, t2, A.a12 * A.a21 * t3));
+    r.j3 = fma_(-(t1 * t2) * t3, kTwentySeventh, fma_(mixed, kThird, off3));
+    // Delta (Alg. alg:disc-stable)
+    double u[14], v[14];
+    dx_fma(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, u);
+    dx_fma(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, v); // M = A^T
+    r.disc = sum_wuv(u, v);
+    return r;
+}
+
+// --------------------------------------------------------------- symmetric
+struct Sym {
+    double s00, s11, s22, s01, s02, s12;
+};
+
+// For a symmetric matrix u = v, r1 = 0, r2 = r7, r3 = r5, r4 = r6, so
+// Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2: a sum of
+// squares with positive weights (no cancellation in the final sum).
+__device__ __forceinline__ Inv invariants_symmetric_fma(const Sym &S)
+{
+    Inv r;
+    const Diag g = diag_part(S.s00, S.s11, S.s22);
+    r.i1 = g.i1;
+    const double q01 = S.s01 * S.s01, q02 = S.s02 * S.s02, q12 = S.s12 * S.s12;
+    r.j2 = fma_(fma_(g.d0, g.d0, fma_(g.d1, g.d1, g.d2 * g.d2)), kSixth, q01 + (q02 + q12));
+    const double t1 = g.d1 + g.d2, t2 = g.d0 - g.d2, t3 = -g.d0 - g.d1;
+    const double off3 = 2.0 * (S.s01 * S.s12 * S.s02);
+    const double mixed = fma_(q01, t1, fma_(q02, t2, q12 * t3));
+    r.j3 = fma_(-(t1 * t2) * t3, kTwentySeventh, fma_(mixed, kThird, off3));
+    const double d0 = g.d0, d1 = g.d1, d2 = g.d2;
+    const double a = S.s01, b = S.s02, c = S.s12;
+    const double ab = a * b, ac = a * c, bc = b * c;
+    const double u2 = fma_(-ab, d2, (q01 - q02) * c);
+    const double u3 = fma_(ac, d1, fma_(-q01, b, q12 * b));
+    const double u4 = fma_(bc, d0, fma_(-q02, a, q12 * a));
+    const double d0d1 = d0 * d1, d1d2 = d1 * d2, d0d2 = d0 * d2;
+    const double u8 = fma_(c, d0d1, fma_(-ab, d1, (q01 - q12) * c));
+    const double u9 = fma_(c, d0d1, fma_(-ab, d0, (q02 - q12) * c));
+    const double u10 = fma_(a, d1d2, fma_(bc, d2, (q02 - q01) * a));
+    const double u11 = fma_(a, d1d2, fma_(bc, d1, (q12 - q01) * a));
+    const double u12 = fma_(-b, d0d2, fma_(ac, d0, (q12 - q02) * b));
+    const double u13 = fma_(b, d0d2, fma_(ac, d2, (q02 - q01) * b));
+    const double u14 = fma_(d0d1, d2, fma_(-q01, d0, fma_(q02, d1, -q12 * d2)));
+    double s = u14 * u14;
+    s = fma_(2.0 * u13, u13, s);
+    s = fma_(2.0 * u12, u12, s);
+    s = fma_(2.0 * u11, u11, s);
+    s = fma_(2.0 * u10, u10, s);
+    s = fma_(2.0 * u9, u9, s);
+    s = fma_(2.0 * u8, u8, s);
+    s = fma_(14.0 * u4, u4, s);
+    s = fma_(14.0 * u3, u3, s);
+    s = fma_(14.0 * u2, u2, s);
+    r.disc = s;
+    return r;
+}
+
+// ============================================================ COMPENSATED
+// Same algorithms; every sum of (triple) products is accumulated with exact
+// pair products and TwoSum, so that each r_i, J2 and J3 carries the accuracy
+// of twice the working precision before its final rounding.
+
+template <class T>
+__device__ __forceinline__ void dx_comp(T M01, T M02, T M10, T M12, T M20, T M21, T d0, T d1, T d2,
+                                        const PairT<T> &d0d1, const PairT<T> &d1d2, const PairT<T> &d0d2,
+                                        T rh[14], T rl[14])
+{
+    const PairT<T> m01m12 = pair(M01, M12), m02m10 = pair(M02, M10), m01m02 = pair(M01, M02);
+    const PairT<T> m01m01 = pair(M01, M01), m02m02 = pair(M02, M02), m01m21 = pair(M01, M21);
+    const PairT<T> m02m21 = pair(M02, M21), m02m12 = pair(M02, M12), m01m10 = pair(M01, M10);
+    const PairT<T> m12m12 = pair(M12, M12), m02m20 = pair(M02, M20), m12m21 = pair(M12, M21);
+    AccT<T> a;
+#define EIG3_R(i, expr)          \
+    {                            \
+        expr;                    \
+        a.split(rh[i], rl[i]);   \
+    }
+    EIG3_R(0, a.first(m01m12, M20); a.add(neg(m02m10), M21))
+    EIG3_R(1, a.first(neg(m01m02), d2); a.add(m01m01, M12); a.add(neg(m02m02), M21))
+    EIG3_R(2, a.first(m01m21, d1); a.add(neg(m01m01), M20); a.add(m02m21, M21))
+    EIG3_R(3, a.first(m02m12, d0); a.add(m01m12, M12); a.add(neg(m02m02), M10))
+    EIG3_R(4, a.first(m01m12, d1); a.add(neg(m01m02), M10); a.add(m02m12, M21))
+    EIG3_R(5, a.first(m02m21, d0); a.add(neg(m01m02), M20); a.add(m01m12, M21))
+    EIG3_R(6, a.first(neg(m02m10), d2); a.add(m01m10, M12); a.add(neg(m02m12), M20))
+    EIG3_R(7, a.first(d0d1, M12); a.add(neg(m02m10), d1); a.add(m01m10, M12); a.add(neg(m12m12), M21))
+    EIG3_R(8, a.first(d0d1, M12); a.add(neg(m02m10), d0); a.add(m02m12, M20); a.add(neg(m12m12), M21))
+    EIG3_R(9, a.first(d1d2, M01); a.add(m02m21, d2); a.add(m01m02, M20); a.add(neg(m01m01), M10))
+    EIG3_R(10, a.first(d1d2, M01); a.add(m02m21, d1); a.add(m01m12, M21); a.add(neg(m01m01), M10))
+    EIG3_R(11, a.first(neg(d0d2), M02); a.add(m01m12, d0); a.add(m02m12, M21); a.add(neg(m02m02), M20))
+    EIG3_R(12, a.first(d0d2, M02); a.add(m01m12, d2); a.add(neg(m01m02), M10); a.add(m02m02, M20))
+    EIG3_R(13, a.first(d0d1, d2); a.add(neg(m01m10), d0); a.add(m02m20, d1); a.add(neg(m12m21), d2))
+#undef EIG3_R
+}
+
+// sum_i w_i u_i v_i with u, v given as hi + lo; weights scale exactly except
+// 6 and 9, which are applied as exact pair products.
+__device__ __forceinline__ double sum_wuv_comp(const double uh[14], const double ul[14], const double vh[14],
+                                               const double vl[14])
+{
+    const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
+    double s, c;
+    {
+        double p, pe;
+        two_prod(uh[0], vh[0], p, pe);
+        s = w[0] * p;
+        c = w[0] * fma_(uh[0], vl[0], fma_(ul[0], vh[0], pe));
+        // w[0] * p is exact up to one rounding; keep its error
+        c = c + fma_(w[0], p, -s);
+    }
+#pragma unroll
+    for (int i = 1; i < 14; ++i) {
+        double p, pe, wp, wpe, t, te;
+        two_prod(uh[i], vh[i], p, pe);
+        two_prod(w[i], p, wp, wpe);
+        two_sum(s, wp, t, te);
+        s = t;
+        c = c + (te + fma_(w[i], fma_(uh[i], vl[i], fma_(ul[i], vh[i], pe)), wpe));
+    }
+    return s + c;
+}
+
+__device__ __forceinline__ Inv invariants_general_comp(const Gen &A)
+{
+    Inv r;
+    const Diag g = diag_part(A.a00, A.a11, A.a22);
+    r.i1 = g.i1;
+    // J2: the sum of squares needs no compensation; the off-diagonal products do
+    {
+        const Pair p01 = pair(A.a01, A.a10), p02 = pair(A.a02, A.a20), p12 = pair(A.a12, A.a21);
+        const double sq = fma_(g.d0, g.d0, fma_(g.d1, g.d1, g.d2 * g.d2)) * kSixth;
+        double s, e1, t, e2;
+        two_sum(p01.hi, p02.hi, s, e1);
+        two_sum(s, p12.hi, t, e2);
+        double u, e3;
+        two_sum(t, sq, u, e3);
+        r.j2 = u + (((e1 + e2) + e3) + ((p01.lo + p02.lo) + p12.lo));
+    }
+    // J3: 27 J3 = 27 offdiag + 9 mixed - t1 t2 t3, accumulated compensated
+    // (the t's are rounded sums of two differences; their rounding is the
+    // backward error the paper's analysis allows)
+    {
+        const double t1 = g.d1 + g.d2, t2 = g.d0 - g.d2, t3 = -g.d0 - g.d1;
+        Acc a;
+        a.first(pair(27.0 * A.a01, A.a12), A.a20);
+        a.add(pair(27.0 * A.a02, A.a10), A.a21);
+        a.add(pair(9.0 * A.a01, A.a10), t1);
+        a.add(pair(9.0 * A.a02, A.a20), t2);
+        a.add(pair(9.0 * A.a12, A.a21), t3);
+        a.add(pair(-t1, t2), t3);
+        r.j3 = a.value() * kTwentySeventh;
+    }
+    // Delta
+    {
+        const Pair d0d1 = pair(g.d0, g.d1), d1d2 = pair(g.d1, g.d2), d0d2 = pair(g.d0, g.d2);
+        double uh[14], ul[14], vh[14], vl[14];
+        dx_comp(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, uh, ul);
+        dx_comp(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, vh, vl);
+        r.disc = sum_wuv_comp(uh, ul, vh, vl);
+    }
+    return r;
+}
+
+__device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
+{
+    // the symmetric path is exactly the general one with A^T = A; u = v
+    // keeps the final sum a sum of nonnegative terms
+    Gen A{S.s00, S.s01, S.s02, S.s01, S.s11, S.s12, S.s02, S.s12, S.s22};
+    Inv r;
+    const Diag g = diag_part(S.s00, S.s11, S.s22);
+    r.i1 = g.i1;
+    const double q01 = S.s01 * S.s01, q02 = S.s02 * S.s02, q12 = S.s12 * S.s12;
+    r.j2 = fma_(fma_(g.d0, g.d0, fma_(g.d1, g.d1, g.d2 * g.d2)), kSixth, q01 + (q02 + q12));
+    {
+        const double t1 = g.d1 + g.d2, t2 = g.d0 - g.d2, t3 = -g.d0 - g.d1;
+        Acc a;
+        a.first(pair(54.0 * S.s01, S.s12), S.s02);
+        a.add(pair(9.0 * S.s01, S.s01), t1);
+        a.add(pair(9.0 * S.s02, S.s02), t2);
+        a.add(pair(9.0 * S.s12, S.s12), t3);
+        a.add(pair(-t1, t2), t3);
+        r.j3 = a.value() * kTwentySeventh;
+    }
+    {
+        const Pair d0d1 = pair(g.d0, g.d1), d1d2 = pair(g.d1, g.d2), d0d2 = pair(g.d0, g.d2);
+        double uh[14], ul[14];
+        dx_comp(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, uh, ul);
+        // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2 (+ 9 u1^2, u1 ~ 0)
+        double s = 0.0, c = 0.0;
+        const double w[14] = {9, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
+#pragma unroll
+        for (int i = 0; i < 14; ++i) {
+            if (w[i] == 0.0)
+                continue;
+            double p, pe, wp, wpe, t, te;
+            two_prod(uh[i], uh[i], p, pe);
+            two_prod(w[i], p, wp, wpe);
+            two_sum(s, wp, t, te);
+            s = t;
+            c = c + (te + fma_(w[i], fma_(2.0 * uh[i], ul[i], pe), wpe));
+        }
+        r.disc = s + c;
+    }
+    return r;
+}
+
+// ============================================================ eigenvalues
+// lambda_k = I1/3 + mu_k with the deviatoric eigenvalues mu_k = 2 sqrt(J2/3)
+// cos((phi + 2 pi k)/3), phi = atan2(sqrt(27 Delta), 27 J3) in [0, pi]
+// (Eq. eigvals-trig with the atan2 reading of Eq. triple-angle-arctan).
+// Evaluated through psi = atan2(sqrt(27 Delta), 27 |J3|) in [0, pi/2]: the
+// roots for -J3 are the negated roots for J3, so for J3 < 0 the values are
+// negated and reversed.  t = psi/3 stays in [0, pi/6], both coalescence
+// limits (phi -> 0 and phi -> pi) become small angles, the three gaps
+//   mu3 - mu1 = r (3c + sqrt3 s), mu3 - mu2 = r (3c - sqrt3 s),
+//   mu2 - mu1 = 2 sqrt3 r s          (r = sqrt(J2/3), c = cos t, s = sin t)
+// have no cancellation, and mu1 <= mu2 <= mu3 holds after rounding.
+struct Trig {
+    double mean; // I1 / 3
+    double r;    // sqrt(J2 / 3)
+    double c, s; // cos t, sin t
+    bool neg;    // J3 < 0
+};
+
+constexpr double kSqrt3 = 1.7320508075688772935;
+
+__device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
+{
+    Trig t;
+    const double disc = fmax(v.disc, 0.0);
+    const double j2 = fmax(v.j2, 0.0);
+    const double psi = atan2(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
+    sincos(psi * kThird, &t.s, &t.c);
+    t.r = sqrt(j2 * kThird);
+    t.mean = v.i1 * kThird;
+    t.neg = v.j3 < 0.0;
+    return t;
+}
+
+__device__ __forceinline__ void mu_from_trig(const Trig &t, double &m1, double &m2, double &m3)
+{
+    const double a1 = -t.r * fma_(kSqrt3, t.s, t.c);
+    const double a2 = t.r * fma_(kSqrt3, t.s, -t.c);
+    const double a3 = 2.0 * t.r * t.c;
+    m1 = t.neg ? -a3 : a1;
+    m2 = t.neg ? -a2 : a2;
+    m3 = t.neg ? -a1 : a3;
+}
+
+__device__ __forceinline__ void eigvals_from_invariants(const Inv &v, double &l1, double &l2, double &l3)
+{
+    const Trig t = trig_from_invariants(v);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    l1 = t.mean + m1;
+    l2 = t.mean + m2;
+    l3 = t.mean + m3;
+}
+
+// ============================================================== backward
+// d(lambda_k)/dA = I/3 + (mu_k S^T + dev(cof S)) / ((lambda_k - lambda_i)(lambda_k - lambda_j)),
+// S = dev A.  Implicit differentiation of mu_k^3 - J2 mu_k - J3 = 0 gives
+// d mu_k = (mu_k dJ2 + dJ3) / (3 mu_k^2 - J2), 3 mu_k^2 - J2 = prod_{j != k}(mu_k - mu_j),
+// with dJ2 = <S^T, dA> (Lemma lem:J2-condition) and dJ3 = <dev cof S, dA>
+// (Lemma lem:J3-jacobian).  The vector-Jacobian product is
+//   grad = (g1 + g2 + g3)/3 I + a S^T + b dev(cof S),
+//   a = sum_k g_k mu_k / G_k, b = sum_k g_k / G_k, G_k the gap products.
+struct Coef {
+    double gsum3; // (g1 + g2 + g3) / 3
+    double a, b;
+};
+
+__device__ __forceinline__ Coef backward_coefficients(const Inv &v, double g1, double g2, double g3)
+{
+    const Trig t = trig_from_invariants(v);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    // gaps of the |J3| configuration; for J3 < 0 they swap roles
+    const double e13 = t.r * fma_(3.0, t.c, kSqrt3 * t.s);
+    const double e23p = t.r * fma_(3.0, t.c, -kSqrt3 * t.s);
+    const double e12p = 2.0 * kSqrt3 * t.r * t.s;
+    const double e12 = t.neg ? e23p : e12p; // mu2 - mu1
+    const double e23 = t.neg ? e12p : e23p; // mu3 - mu2
+    const double G1 = e12 * e13;   // (mu1 - mu2)(mu1 - mu3)
+    const double G2 = -e12 * e23;  // (mu2 - mu1)(mu2 - mu3)
+    const double G3 = e13 * e23;   // (mu3 - mu1)(mu3 - mu2)
+    const double q1 = g1 / G1, q2 = g2 / G2, q3 = g3 / G3;
+    Coef c;
+    c.gsum3 = (g1 + g2 + g3) * kThird;
+    c.b = q1 + q2 + q3;
+    c.a = fma_(q1, m1, fma_(q2, m2, q3 * m3));
+    return c;
+}
+
+// grad (row-major 9) for a general matrix
+__device__ __forceinline__ void backward_general(const Gen &A, const Coef &k, double grad[9])
+{
+    const Diag g = diag_part(A.a00, A.a11, A.a22);
+    // S = dev A from the differences (no rounding of I1/3 enters)
+    const double s00 = (g.d0 + g.d1) * kThird, s11 = (g.d2 - g.d0) * kThird, s22 = -(g.d1 + g.d2) * kThird;
+    const double s01 = A.a01, s02 = A.a02, s10 = A.a10, s12 = A.a12, s20 = A.a20, s21 = A.a21;
+    // cofactor matrix of S
+    double c00 = fma_(s11, s22, -s12 * s21);
+    double c01 = fma_(s12, s20, -s10 * s22);
+    double c02 = fma_(s10, s21, -s11 * s20);
+    double c10 = fma_(s02, s21, -s01 * s22);
+    double c11 = fma_(s00, s22, -s02 * s20);
+    double c12 = fma_(s01, s20, -s00 * s21);
+    double c20 = fma_(s01, s12, -s02 * s11);
+    double c21 = fma_(s02, s10, -s00 * s12);
+    double c22 = fma_(s00, s11, -s01 * s10);
+    const double tr3 = ((c00 + c11) + c22) * kThird;
+    c00 -= tr3;
+    c11 -= tr3;
+    c22 -= tr3;
+    grad[0] = fma_(k.a, s00, fma_(k.b, c00, k.gsum3));
+    grad[1] = fma_(k.a, s10, k.b * c01);
+    grad[2] = fma_(k.a, s20, k.b * c02);
+    grad[3] = fma_(k.a, s01, k.b * c10);
+    grad[4] = fma_(k.a, s11, fma_(k.b, c11, k.gsum3));
+    grad[5] = fma_(k.a, s21, k.b * c12);
+    grad[6] = fma_(k.a, s02, k.b * c20);
+    grad[7] = fma_(k.a, s12, k.b * c21);
+    grad[8] = fma_(k.a, s22, fma_(k.b, c22, k.gsum3));
+}
+
+} // namespace eig3

@@ -1,0 +1,119 @@
+"""Degenerate and out-of-contract inputs on the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from accuracy import Truth, check, inv_errors, lam_errors
+from gpu_util import download_inv, download_lam, upload
+
+pytestmark = pytest.mark.gpu
+
+ACCS = ["fma", "compensated"]
+
+
+@pytest.fixture(scope="module")
+def eig3():
+    import paper_2511_00292_amd as m
+    return m
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_scaled_identity_exact(eig3, acc):
+    """fl(J2(alpha I)) = 0 exactly (the remark on Algorithm alg:J2-stable's
+    exactness); J3 and Delta vanish, and lambda = I1/3 three times."""
+    alphas = np.array([0.1, -3.7, 1e-300, 1e300, 12345.678, 0.0])
+    a = np.zeros((alphas.size, 9))
+    a[:, 0] = a[:, 4] = a[:, 8] = alphas
+    inv = download_inv(eig3.eig3_invariants(upload(a, "soa"), "general", acc))
+    assert np.all(inv[:, 1:] == 0.0)
+    lam = download_lam(eig3.eig3_eigvals(upload(a, "aos"), "general", acc))
+    assert np.all(lam == lam[:, :1])
+    assert np.allclose(lam[:, 0], alphas, rtol=4 * 2.0 ** -53, atol=0)
+    s = np.stack([alphas, alphas, alphas, 0 * alphas, 0 * alphas, 0 * alphas], axis=1)
+    invs = download_inv(eig3.eig3_invariants(upload(s, "soa"), "symmetric", acc))
+    assert np.all(invs[:, 1:] == 0.0)
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_triangular_bitwise_equals_diagonal(eig3, acc):
+    rng = np.random.default_rng(41)
+    n = 5000
+    d = rng.standard_normal((n, 3))
+    off = rng.standard_normal((n, 3))
+    up = np.zeros((n, 9)); lo = np.zeros((n, 9)); dg = np.zeros((n, 9))
+    for m in (up, lo, dg):
+        m[:, 0], m[:, 4], m[:, 8] = d[:, 0], d[:, 1], d[:, 2]
+    up[:, 1], up[:, 2], up[:, 5] = off[:, 0], off[:, 1], off[:, 2]
+    lo[:, 3], lo[:, 6], lo[:, 7] = off[:, 0], off[:, 1], off[:, 2]
+    ref = download_inv(eig3.eig3_invariants(upload(dg, "soa"), "general", acc))
+    for t in (up, lo):
+        got = download_inv(eig3.eig3_invariants(upload(t, "soa"), "general", acc))
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_exact_repeated_roots(eig3, acc):
+    cases = [[1, 1, 2], [2, 2, 2], [-1, 3, 3], [0.5, 0.5, -7.25], [1, 2, 3]]
+    a = np.zeros((len(cases), 9))
+    for i, c in enumerate(cases):
+        a[i, 0], a[i, 4], a[i, 8] = c
+    inv = download_inv(eig3.eig3_invariants(upload(a, "soa"), "general", acc))
+    assert np.all(inv[:4, 3] == 0.0)      # Delta = 0 exactly for the repeated roots
+    assert inv[4, 2] == 0.0               # J3 = 0 exactly for diag(1, 2, 3)
+    lam = download_lam(eig3.eig3_eigvals(upload(a, "aos"), "general", acc))
+    ref = np.sort(np.array(cases, dtype=np.float64), axis=1)
+    assert np.allclose(lam, ref, rtol=0, atol=8 * 2.0 ** -53 * np.abs(ref).max(1, keepdims=True) * 3)
+
+
+def test_nan_propagates_per_matrix(eig3):
+    c = w.config1(300, seed=5)
+    a = c["a"].copy()
+    a[17, 4] = np.nan
+    a[200, 2] = np.inf
+    lam = download_lam(eig3.eig3_eigvals(upload(a, "aos")))
+    assert np.all(np.isnan(lam[17]))
+    assert not np.isfinite(lam[200]).all()
+    good = np.ones(300, dtype=bool)
+    good[[17, 200]] = False
+    assert np.isfinite(lam[good]).all()
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_complex_spectrum_stays_finite(eig3, acc):
+    """Outside the precondition (complex pair): Delta < 0 is clamped, results
+    are finite and the real part of the pair is recovered."""
+    th = np.linspace(0.1, 3.0, 50)
+    a = np.zeros((50, 9))
+    a[:, 0] = np.cos(th); a[:, 1] = -np.sin(th); a[:, 3] = np.sin(th); a[:, 4] = np.cos(th); a[:, 8] = 0.3
+    lam = download_lam(eig3.eig3_eigvals(upload(a, "aos"), "general", acc))
+    assert np.isfinite(lam).all()
+    # the real parts cos(th) (twice) and 0.3 are returned, up to the size of
+    # the clamped imaginary part
+    ref = np.sort(np.stack([np.cos(th), np.cos(th), np.full(50, 0.3)], axis=1), axis=1)
+    assert np.all(np.abs(lam - ref) <= np.abs(np.sin(th))[:, None] * 1.01 + 1e-12)
+
+
+def test_zero_matrix_and_empty_batch(eig3):
+    import torch
+    z = np.zeros((3, 9))
+    assert np.all(download_lam(eig3.eig3_eigvals(upload(z, "aos"))) == 0.0)
+    e = torch.empty((0, 9), dtype=torch.float64, device="cuda:0")
+    out = eig3.eig3_eigvals(e)
+    assert out.shape == (0, 3)
+    inv = eig3.eig3_invariants(e)
+    assert all(x.numel() == 0 for x in inv)
+
+
+@pytest.mark.parametrize("scale", [1e-40, 1e-10, 1e10, 1e40])
+def test_scaling_range(eig3, scale):
+    """Delta is a sixth-degree form: entries up to ~1e50 keep it in range."""
+    c = w.config1(500, seed=6)
+    a = c["a"] * scale
+    t = Truth(a, c["kappa"])
+    lam = download_lam(eig3.eig3_eigvals(upload(a, "aos")))
+    check(lam_errors(t, lam), t.bound_lam(), what=f"scale {scale}")
+    inv = download_inv(eig3.eig3_invariants(upload(a, "soa")))
+    check(inv_errors(t, inv), t.bound_inv(), what=f"invariants scale {scale}")
+    assert math.isfinite(float(np.abs(inv).max()))
