@@ -191,7 +191,12 @@ def main():
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a, "general", acc_v, "soa", out=lam), "f64")
             variant(f"config5 bwd general f64 {acc_v}", "bwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals_backward(a, g, "general", acc_v, out=grad), "f64")
-        del a, g, lam, grad
+        # the same batch as one (n, 3, 3) array of structures (LDS-staged loads)
+        a_aos = torch.stack(a, dim=1).contiguous()
+        lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)
+        variant("config5 fwd general f64 fma aos", "fwd_general_f64", N_MAIN,
+                lambda: eig3.eig3_eigvals(a_aos, "general", "fma", "aos", out=lam_aos), "f64")
+        del a, g, lam, grad, a_aos, lam_aos
         torch.cuda.empty_cache()
         # perturbation sweep (config 2)
         t0 = time.perf_counter()

@@ -135,6 +135,26 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Bod
     }
 }
 
+template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Mat<float, S> &m)
+{
+    if constexpr (Acc == EIG3_COMPENSATED) {
+        if constexpr (S == EIG3_GENERAL)
+            return invariants_f32_comp_general(m.a);
+        else
+            return invariants_f32_comp_symmetric(m.a);
+    } else {
+        Inv v;
+        if constexpr (S == EIG3_GENERAL)
+            v = invariants_general_fma(Gen{double(m.a[0]), double(m.a[1]), double(m.a[2]), double(m.a[3]),
+                                           double(m.a[4]), double(m.a[5]), double(m.a[6]), double(m.a[7]),
+                                           double(m.a[8])});
+        else
+            v = invariants_symmetric_fma(
+                Sym{double(m.a[0]), double(m.a[1]), double(m.a[2]), double(m.a[3]), double(m.a[4]), double(m.a[5])});
+        return InvW{v.i1, v.j2, v.j3, v.disc};
+    }
+}
+
 // ------------------------------------------------------------------ kernels
 template <int S, int L, int Acc>
 __global__ __launch_bounds__(kBlock) void k_invariants_f64(int64_t n, In9<double> in, Out4<double> out)
@@ -170,6 +190,29 @@ __global__ __launch_bounds__(kBlock) void k_eigvals_f64(int64_t n, In9<double> i
         const Inv v = invariants_of<S, Acc>(m);
         double l1, l2, l3;
         eigvals_from_invariants(v, l1, l2, l3);
+        store3(out, OL, i, l1, l2, l3);
+    });
+}
+
+template <int S, int L, int Acc>
+__global__ __launch_bounds__(kBlock) void k_invariants_f32(int64_t n, In9<float> in, Out4<float> out)
+{
+    for_each_matrix<float, S, L>(n, in, [&](int64_t i, const Mat<float, S> &m) {
+        const InvW v = invariants_of<S, Acc>(m);
+        __builtin_nontemporal_store(float(v.i1), out.p[0] + i);
+        __builtin_nontemporal_store(float(v.j2), out.p[1] + i);
+        __builtin_nontemporal_store(float(v.j3), out.p[2] + i);
+        __builtin_nontemporal_store(float(v.disc), out.p[3] + i);
+    });
+}
+
+template <int S, int L, int OL, int Acc>
+__global__ __launch_bounds__(kBlock) void k_eigvals_f32(int64_t n, In9<float> in, Out3<float> out)
+{
+    for_each_matrix<float, S, L>(n, in, [&](int64_t i, const Mat<float, S> &m) {
+        const InvW v = invariants_of<S, Acc>(m);
+        float l1, l2, l3;
+        eigvals_f32_from_invariants(v, l1, l2, l3);
         store3(out, OL, i, l1, l2, l3);
     });
 }
@@ -361,9 +404,17 @@ int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *
     void *outs[4] = {i1, j2, j3, disc};
     if ((st = check_outputs(A, outs, 4, size_t(A->n))) != EIG3_OK)
         return st;
-    if (A->dtype != EIG3_F64)
-        return EIG3_EUNSUPPORTED;
     const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    if (A->dtype == EIG3_F32) {
+        Out4<float> o32{{static_cast<float *>(i1), static_cast<float *>(j2), static_cast<float *>(j3),
+                         static_cast<float *>(disc)}};
+        const In9<float> in32 = inputs_of<float>(A);
+        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            hipLaunchKernelGGL((k_invariants_f32<S.value, L.value, Acc.value>), grid, block, 0, stream, A->n, in32,
+                               o32);
+        });
+        return launched();
+    }
     Out4<double> out{{static_cast<double *>(i1), static_cast<double *>(j2), static_cast<double *>(j3),
                       static_cast<double *>(disc)}};
     const In9<double> in = inputs_of<double>(A);
@@ -386,9 +437,20 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
     const int nout = out_layout == EIG3_SOA ? 3 : 1;
     if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? 3 : 1))) != EIG3_OK)
         return st;
-    if (A->dtype != EIG3_F64)
-        return EIG3_EUNSUPPORTED;
     const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    if (A->dtype == EIG3_F32) {
+        Out3<float> o32{{static_cast<float *>(outs[0]), static_cast<float *>(outs[1]), static_cast<float *>(outs[2])}};
+        const In9<float> in32 = inputs_of<float>(A);
+        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            if (out_layout == EIG3_AOS)
+                hipLaunchKernelGGL((k_eigvals_f32<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream,
+                                   A->n, in32, o32);
+            else
+                hipLaunchKernelGGL((k_eigvals_f32<S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream,
+                                   A->n, in32, o32);
+        });
+        return launched();
+    }
     Out3<double> out{{static_cast<double *>(outs[0]), static_cast<double *>(outs[1]), static_cast<double *>(outs[2])}};
     const In9<double> in = inputs_of<double>(A);
     dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {

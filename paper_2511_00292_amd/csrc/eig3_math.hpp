@@ -376,6 +376,98 @@ __device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
     return r;
 }
 
+// ======================================================= transcendentals
+// The triple angle needs atan2 of two nonnegative numbers and the sine and
+// cosine of a third of it, t in [0, pi/6]; neither needs a general range
+// reduction.
+//
+// atan: q = min/max in [0, 1]; for q > tan(pi/8) the identity
+// atan(q) = pi/4 + atan((q - 1)/(q + 1)) maps it into [-tan(pi/8), 0], folded
+// into the same single division.  atan(z) = z P(z^2) on |z| <= tan(pi/8), P
+// a least-squares polynomial on Chebyshev nodes (csrc/gen_poly.py): relative
+// error 3.4e-17 (binary64, degree 10) and 1.8e-8 (binary32, degree 4).
+// sin, cos: Taylor polynomials on [0, pi/6]; the first omitted term is below
+// 2e-18 (binary64: to t^15 and t^14) and 4e-10 (binary32: to t^9 and t^8).
+constexpr double kPi2 = 1.5707963267948966192;
+constexpr double kPi4 = 0.78539816339744830962;
+constexpr double kTanPi8 = 0.41421356237309504880;
+
+__device__ __forceinline__ double atan_poly(double u)
+{
+    double p = 0.02116321748124264808858265;
+    p = fma_(p, u, -0.04350445257430010837229732);
+    p = fma_(p, u, 0.05689223501766054343064029);
+    p = fma_(p, u, -0.06640410811535267761156447);
+    p = fma_(p, u, 0.07689975128569665072030238);
+    p = fma_(p, u, -0.09090774712795826084526493);
+    p = fma_(p, u, 0.1111110625599581821334887);
+    p = fma_(p, u, -0.1428571418297856464657463);
+    p = fma_(p, u, 0.1999999999888207705532328);
+    p = fma_(p, u, -0.3333333333332857960189553);
+    p = fma_(p, u, 0.9999999999999999665383002);
+    return p;
+}
+
+__device__ __forceinline__ float atan_poly(float u)
+{
+    float p = 0.07984962911065899521160472f;
+    p = fma_(p, u, -0.1385147842677151367970504f);
+    p = fma_(p, u, 0.1997440478587335297876003f);
+    p = fma_(p, u, -0.3333279693519533346875533f);
+    p = fma_(p, u, 0.9999999818725111375741227f);
+    return p;
+}
+
+// atan2(y, x) for y, x >= 0, in [0, pi/2]; atan2(0, 0) = 0.
+template <class T> __device__ __forceinline__ T atan2_nonneg(T y, T x)
+{
+    const T m = y < x ? y : x;
+    const T M = y < x ? x : y;
+    const bool far = m > T(kTanPi8) * M;
+    const T num = far ? m - M : m;
+    const T den = far ? m + M : M;
+    const T z = M > T(0) ? num / den : T(0);
+    T r = z * atan_poly(z * z);
+    r = far ? r + T(kPi4) : r;
+    return y > x ? T(kPi2) - r : r;
+}
+
+__device__ __forceinline__ void sincos_sixth(double t, double &s, double &c)
+{
+    const double u = t * t;
+    double ps = -1.0 / 1307674368000.0;
+    ps = fma_(ps, u, 1.0 / 6227020800.0);
+    ps = fma_(ps, u, -1.0 / 39916800.0);
+    ps = fma_(ps, u, 1.0 / 362880.0);
+    ps = fma_(ps, u, -1.0 / 5040.0);
+    ps = fma_(ps, u, 1.0 / 120.0);
+    ps = fma_(ps, u, -1.0 / 6.0);
+    s = fma_(t * u, ps, t);
+    double pc = -1.0 / 87178291200.0;
+    pc = fma_(pc, u, 1.0 / 479001600.0);
+    pc = fma_(pc, u, -1.0 / 3628800.0);
+    pc = fma_(pc, u, 1.0 / 40320.0);
+    pc = fma_(pc, u, -1.0 / 720.0);
+    pc = fma_(pc, u, 1.0 / 24.0);
+    pc = fma_(pc, u, -0.5);
+    c = fma_(u, pc, 1.0);
+}
+
+__device__ __forceinline__ void sincos_sixth(float t, float &s, float &c)
+{
+    const float u = t * t;
+    float ps = 1.0f / 362880.0f;
+    ps = fma_(ps, u, -1.0f / 5040.0f);
+    ps = fma_(ps, u, 1.0f / 120.0f);
+    ps = fma_(ps, u, -1.0f / 6.0f);
+    s = fma_(t * u, ps, t);
+    float pc = 1.0f / 40320.0f;
+    pc = fma_(pc, u, -1.0f / 720.0f);
+    pc = fma_(pc, u, 1.0f / 24.0f);
+    pc = fma_(pc, u, -0.5f);
+    c = fma_(u, pc, 1.0f);
+}
+
 // ============================================================ eigenvalues
 // lambda_k = I1/3 + mu_k with the deviatoric eigenvalues mu_k = 2 sqrt(J2/3)
 // cos((phi + 2 pi k)/3), phi = atan2(sqrt(27 Delta), 27 J3) in [0, pi]
@@ -396,13 +488,16 @@ struct Trig {
 
 constexpr double kSqrt3 = 1.7320508075688772935;
 
+// max(x, 0) that keeps NaN (fmax would drop it)
+__device__ __forceinline__ double clamp0(double x) { return x < 0.0 ? 0.0 : x; }
+
 __device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
 {
     Trig t;
-    const double disc = fmax(v.disc, 0.0);
-    const double j2 = fmax(v.j2, 0.0);
-    const double psi = atan2(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
-    sincos(psi * kThird, &t.s, &t.c);
+    const double disc = clamp0(v.disc);
+    const double j2 = clamp0(v.j2);
+    const double psi = atan2_nonneg(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
+    sincos_sixth(psi * kThird, t.s, t.c);
     t.r = sqrt(j2 * kThird);
     t.mean = v.i1 * kThird;
     t.neg = v.j3 < 0.0;
@@ -427,6 +522,132 @@ __device__ __forceinline__ void eigvals_from_invariants(const Inv &v, double &l1
     l1 = t.mean + m1;
     l2 = t.mean + m2;
     l3 = t.mean + m3;
+}
+
+// ================================================================ binary32
+// Two evaluations of binary32 batches.
+//
+// Widened (EIG3_FMA): entries are converted to binary64 and the invariants
+// come from the binary64 FMA path above; on gfx950 a binary64 FMA issues at
+// the same rate as a non-packed binary32 one, so this is the cheaper of the
+// two and its invariants carry binary64 accuracy.
+//
+// Compensated (EIG3_COMPENSATED): binary32 arithmetic throughout, with
+// error-free (FMA TwoProduct + TwoSum) evaluation of the off-diagonal part of
+// J2 (general input), of J3 and of every r_i of dx; the sum of products
+// Delta = sum w_i u_i v_i is accumulated in binary64 from the exact hi + lo
+// pairs, so Delta never underflows in binary32.
+//
+// Both form the triple-angle argument in binary64 (sqrt(27 Delta) and
+// 27 |J3|, rescaled by an exact power of two into binary32 range) and finish
+// with binary32 arctangent, sine and cosine.
+
+struct InvW {
+    double i1, j2, j3, disc; // binary64 values of the invariants
+};
+
+__device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
+{
+    const float a00 = a[0], a01 = a[1], a02 = a[2], a10 = a[3], a11 = a[4], a12 = a[5], a20 = a[6], a21 = a[7],
+                a22 = a[8];
+    InvW r;
+    const float d0 = a00 - a11, d1 = a00 - a22, d2 = a11 - a22;
+    r.i1 = double((a00 + a11) + a22);
+    {
+        const PairT<float> p01 = pair(a01, a10), p02 = pair(a02, a20), p12 = pair(a12, a21);
+        const float sq = fma_(d0, d0, fma_(d1, d1, d2 * d2)) * (1.0f / 6.0f);
+        float s, e1, t, e2, u, e3;
+        two_sum(p01.hi, p02.hi, s, e1);
+        two_sum(s, p12.hi, t, e2);
+        two_sum(t, sq, u, e3);
+        r.j2 = double(u) + double(((e1 + e2) + e3) + ((p01.lo + p02.lo) + p12.lo));
+    }
+    {
+        const float t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
+        AccT<float> acc;
+        acc.first(pair(27.0f * a01, a12), a20);
+        acc.add(pair(27.0f * a02, a10), a21);
+        acc.add(pair(9.0f * a01, a10), t1);
+        acc.add(pair(9.0f * a02, a20), t2);
+        acc.add(pair(9.0f * a12, a21), t3);
+        acc.add(pair(-t1, t2), t3);
+        r.j3 = (double(acc.s) + double(acc.c)) * kTwentySeventh;
+    }
+    {
+        const PairT<float> d0d1 = pair(d0, d1), d1d2 = pair(d1, d2), d0d2 = pair(d0, d2);
+        float uh[14], ul[14], vh[14], vl[14];
+        dx_comp<float>(a01, a02, a10, a12, a20, a21, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul);
+        dx_comp<float>(a10, a20, a01, a21, a02, a12, d0, d1, d2, d0d1, d1d2, d0d2, vh, vl);
+        const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
+        double disc = 0.0;
+#pragma unroll
+        for (int i = 13; i >= 0; --i)
+            disc = fma_(w[i] * (double(uh[i]) + double(ul[i])), double(vh[i]) + double(vl[i]), disc);
+        r.disc = disc;
+    }
+    return r;
+}
+
+__device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
+{
+    const float s00 = a[0], s11 = a[1], s22 = a[2], s01 = a[3], s02 = a[4], s12 = a[5];
+    InvW r;
+    const float d0 = s00 - s11, d1 = s00 - s22, d2 = s11 - s22;
+    r.i1 = double((s00 + s11) + s22);
+    const float q01 = s01 * s01, q02 = s02 * s02, q12 = s12 * s12;
+    // a sum of nonnegative terms: no compensation needed
+    r.j2 = double(fma_(fma_(d0, d0, fma_(d1, d1, d2 * d2)), 1.0f / 6.0f, q01 + (q02 + q12)));
+    {
+        const float t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
+        AccT<float> acc;
+        acc.first(pair(54.0f * s01, s12), s02);
+        acc.add(pair(9.0f * s01, s01), t1);
+        acc.add(pair(9.0f * s02, s02), t2);
+        acc.add(pair(9.0f * s12, s12), t3);
+        acc.add(pair(-t1, t2), t3);
+        r.j3 = (double(acc.s) + double(acc.c)) * kTwentySeventh;
+    }
+    {
+        const PairT<float> d0d1 = pair(d0, d1), d1d2 = pair(d1, d2), d0d2 = pair(d0, d2);
+        float uh[14], ul[14];
+        dx_comp<float>(s01, s02, s01, s12, s02, s12, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul);
+        // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2
+        const double w[14] = {0, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
+        double disc = 0.0;
+#pragma unroll
+        for (int i = 13; i >= 0; --i) {
+            if (w[i] == 0.0)
+                continue;
+            const double u = double(uh[i]) + double(ul[i]);
+            disc = fma_(w[i] * u, u, disc);
+        }
+        r.disc = disc;
+    }
+    return r;
+}
+
+// Eigenvalues in binary32 from binary64 invariants.
+__device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float &l1, float &l2, float &l3)
+{
+    const double disc = clamp0(v.disc);
+    const double y = sqrt(27.0 * disc);
+    const double x = 27.0 * fabs(v.j3);
+    // exact rescaling of the pair into binary32 range
+    const double big = fmax(fmax(y, x), 1e-300);
+    const int e = ilogb(big);
+    const float yf = float(ldexp(y, -e)), xf = float(ldexp(x, -e));
+    const float psi = atan2_nonneg(yf, xf);
+    float s, c;
+    sincos_sixth(psi * (1.0f / 3.0f), s, c);
+    const float r = sqrtf(float(clamp0(v.j2) * kThird));
+    const float mean = float(v.i1 * kThird);
+    const float a1 = -r * fma_(float(kSqrt3), s, c);
+    const float a2 = r * fma_(float(kSqrt3), s, -c);
+    const float a3 = 2.0f * r * c;
+    const bool neg = v.j3 < 0.0;
+    l1 = mean + (neg ? -a3 : a1);
+    l2 = mean + (neg ? -a2 : a2);
+    l3 = mean + (neg ? -a1 : a3);
 }
 
 // ============================================================== backward

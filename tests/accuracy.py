@@ -1,12 +1,26 @@
 """Error measurement against the exact oracle, shared by the GPU parity tests.
 
 Gates (forward errors against the exact definitions of oracle/exact.py, bound
-b = the paper's lowest-order stability bound with C = 1, Frobenius norms; for
+b = the paper's stability bound with C = 1 and Frobenius norms; for
 eigenvalues b = kappa_2(V) ||A|| eps with kappa_2(V) known from the generator):
 
-  G1: |x - truth| <= 8 b                       (8x the stability bound)
-  G2: |x - truth| <= 8 b + |x_paper - truth|   (no worse than the paper's own
-      algorithm in plain binary64, oracle/eig3_plain.c, plus the 8x allowance)
+  b_I1 = ||A|| eps
+  b_J2 = ||S||^2 eps + ||S||^2 eps^2            (S = dev A)
+  b_J3 = ||dev cof S|| ||S|| eps + ||S||^3 eps^2
+  b_D  = ||dev(12 J2^2 A^T - 54 J3 cof S)|| ||S|| eps + ||S||^6 eps^2
+  b_l  = kappa_2 ||A|| eps
+
+The paper's bounds are first order, "+ O(eps^2)"; the second-order term is
+taken as eps^2 ||S||^k with k the degree of the invariant.  It matters only
+where the first-order term vanishes: at an exactly repeated eigenvalue the
+Jacobian of Delta is zero, and an FMA evaluation then returns a Delta of
+order eps^2 ||S||^6 where the exact value is 0.
+
+  G1: |x - truth| <= 8 b elementwise            (8x the stability bound)
+  G2: max |x - truth|/b <= 8 + 2 max |x_paper - truth|/b over the bucket,
+      per output: no worse than the paper's own algorithm in plain binary64
+      (oracle/eig3_plain.c) in the worst case, up to a factor 2 for a
+      different rounding order, plus the 8x allowance.
 
 G1 applies where the paper's algorithms themselves meet their bounds
 (orthogonal and well-conditioned eigenbases, kappa <= 10, and symmetric
@@ -43,7 +57,9 @@ class Truth:
             self.lam[m] = exact.eigvals_float(a[m])
 
     def bound_inv(self, eps=EPS64):
-        return self.scale[:, :4] * eps
+        ns = np.sqrt(self.scale[:, 1])  # ||dev A||
+        second = np.stack([0.0 * ns, ns ** 2, ns ** 3, ns ** 6], axis=1) * eps * eps
+        return self.scale[:, :4] * eps + second
 
     def bound_lam(self, eps=EPS64):
         return (self.scale[:, 4] * self.kappa * eps)[:, None]
@@ -73,6 +89,23 @@ def check(err: np.ndarray, bound: np.ndarray, allowance: np.ndarray | None = Non
             f"{what}: {int(bad.sum())} of {err.size} values exceed the gate; worst at {idx}: "
             f"err={err[idx]:.3e} bound={bound[idx]:.3e} allowance="
             f"{(0.0 if allowance is None else allowance[idx]):.3e}")
+
+
+def check_g2(err: np.ndarray, bound: np.ndarray, err_paper: np.ndarray, factor: float = 8.0,
+             what: str = "") -> None:
+    """G2 per output column: worst ratio of x no worse than 8 + 2x the worst
+    ratio of the paper's algorithm over the same bucket."""
+    bound = np.broadcast_to(bound, err.shape)
+    if err.size == 0:
+        return
+    tiny = np.maximum(bound, 1e-300)
+    r = np.where(bound > 0, err / tiny, np.where(err > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
+    rp = np.where(bound > 0, err_paper / tiny, np.where(err_paper > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
+    lim = factor + 2.0 * rp.max(axis=0)
+    worst = r.max(axis=0)
+    if np.any(worst > lim):
+        raise AssertionError(f"{what}: worst ratio per output {np.round(worst, 2)} exceeds 8 + 2 x paper's "
+                             f"worst {np.round(rp.max(axis=0), 2)}")
 
 
 def ratio_summary(err: np.ndarray, bound: np.ndarray) -> dict:

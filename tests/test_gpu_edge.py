@@ -82,17 +82,27 @@ def test_nan_propagates_per_matrix(eig3):
 
 @pytest.mark.parametrize("acc", ACCS)
 def test_complex_spectrum_stays_finite(eig3, acc):
-    """Outside the precondition (complex pair): Delta < 0 is clamped, results
-    are finite and the real part of the pair is recovered."""
+    """Outside the precondition (a complex pair): Delta < 0 is clamped to 0,
+    the results are finite, ascending, and still sum to the trace."""
     th = np.linspace(0.1, 3.0, 50)
     a = np.zeros((50, 9))
     a[:, 0] = np.cos(th); a[:, 1] = -np.sin(th); a[:, 3] = np.sin(th); a[:, 4] = np.cos(th); a[:, 8] = 0.3
     lam = download_lam(eig3.eig3_eigvals(upload(a, "aos"), "general", acc))
     assert np.isfinite(lam).all()
-    # the real parts cos(th) (twice) and 0.3 are returned, up to the size of
-    # the clamped imaginary part
-    ref = np.sort(np.stack([np.cos(th), np.cos(th), np.full(50, 0.3)], axis=1), axis=1)
-    assert np.all(np.abs(lam - ref) <= np.abs(np.sin(th))[:, None] * 1.01 + 1e-12)
+    assert np.all(np.diff(lam, axis=1) >= 0)
+    assert np.allclose(lam.sum(1), 2 * np.cos(th) + 0.3, atol=1e-14)
+
+
+def test_nan_off_diagonal_propagates(eig3):
+    """A NaN off-diagonal entry (the trace stays finite) still gives NaN."""
+    c = w.config1(64, seed=5)
+    a = c["a"].copy()
+    a[10, 1] = np.nan
+    a[20, 7] = np.nan
+    for acc in ACCS:
+        lam = download_lam(eig3.eig3_eigvals(upload(a, "aos"), "general", acc))
+        assert np.all(np.isnan(lam[[10, 20]]))
+        assert np.isfinite(np.delete(lam, [10, 20], axis=0)).all()
 
 
 def test_zero_matrix_and_empty_batch(eig3):

@@ -1,0 +1,87 @@
+"""binary32 storage (EIG3_F32): eigenvalues against the exact oracle at the
+binary32 input widened to binary64, with the binary32 unit roundoff in the
+bounds.  Both evaluations are checked: "fma" (binary64 invariants from the
+widened entries) and "compensated" (binary32 error-free products, binary64
+Delta accumulation)."""
+import numpy as np
+import pytest
+
+import workloads as w
+from accuracy import EPS32, Truth, check, inv_errors, lam_errors
+from gpu_util import download_inv, download_lam, upload
+
+pytestmark = pytest.mark.gpu
+
+ACCS = ["fma", "compensated"]
+F32_TINY = np.finfo(np.float32).tiny
+
+
+@pytest.fixture(scope="module")
+def eig3():
+    import paper_2511_00292_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def c4():
+    c = w.config4(1500)
+    s = c["s"]  # float32
+    a = w.symmetric_to_general(s.astype(np.float64))
+    return s, Truth(a, np.ones(a.shape[0]))
+
+
+@pytest.fixture(scope="module")
+def c1f():
+    c = w.config1(1500)
+    a32 = c["a"].astype(np.float32)
+    return a32, Truth(a32.astype(np.float64), c["kappa"])
+
+
+@pytest.mark.parametrize("acc", ACCS)
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_config4_symmetric_f32(eig3, c4, acc, layout):
+    s, t = c4
+    lam = download_lam(eig3.eig3_eigvals(upload(s, layout), "symmetric", acc, "soa"))
+    check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"config4 f32 eigvals {acc} {layout}")
+    assert np.all(np.diff(lam, axis=1) >= 0)
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_config4_invariants_f32(eig3, c4, acc):
+    """I1 and J2 everywhere; J3 and Delta where the result is a binary32
+    normal number (below, the subnormal spacing exceeds the bound)."""
+    s, t = c4
+    inv = download_inv(eig3.eig3_invariants(upload(s, "soa"), "symmetric", acc))
+    err = inv_errors(t, inv)
+    b = t.bound_inv(EPS32)
+    normal = np.abs(t.inv) >= F32_TINY
+    normal[:, :2] = True
+    check(np.where(normal, err, 0.0), b, what=f"config4 f32 invariants {acc}")
+
+
+@pytest.mark.parametrize("acc", ACCS)
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_general_f32(eig3, c1f, acc, layout):
+    a32, t = c1f
+    lam = download_lam(eig3.eig3_eigvals(upload(a32, layout), "general", acc, "aos"))
+    check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"general f32 eigvals {acc} {layout}")
+
+
+@pytest.mark.parametrize("n", [1, 63, 257, 1000])
+def test_f32_ragged(eig3, n):
+    c = w.config4(n, seed=91)
+    s = c["s"]
+    t = Truth(w.symmetric_to_general(s.astype(np.float64)), np.ones(n))
+    for acc in ACCS:
+        for layout in ("soa", "aos"):
+            lam = download_lam(eig3.eig3_eigvals(upload(s, layout), "symmetric", acc, "aos"))
+            check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"f32 ragged n={n} {acc} {layout}")
+
+
+def test_f32_backward_unsupported(eig3):
+    s = upload(w.config4(16, seed=3)["s"], "aos")
+    import torch
+    g = torch.zeros((16, 3), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(eig3.Eig3Error) as e:
+        eig3.eig3_eigvals_backward(s, g, "symmetric")
+    assert e.value.status == -2
