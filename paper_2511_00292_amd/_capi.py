@@ -10,7 +10,9 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libeig3.so")
+# EIG3_LIBRARY may name another build of the same sources (A/B timing of
+# build-time knobs); by default the in-tree build next to this file is used
+LIB_PATH = os.environ.get("EIG3_LIBRARY") or os.path.join(HERE, "libeig3.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "eig3.h")
 
 # enums of include/eig3.h

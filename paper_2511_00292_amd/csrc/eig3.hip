@@ -22,6 +22,40 @@ using namespace eig3;
 constexpr int kBlock = 256;
 constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 
+// Build-time tuning knobs (defaults are the measured best on MI355X):
+//  EIG3_NONTEMPORAL   1: streaming loads/stores carry the nontemporal hint
+//  EIG3_WAVES_PER_EU  minimum resident waves per SIMD requested from the
+//                     register allocator (0: compiler default)
+#ifndef EIG3_NONTEMPORAL
+#define EIG3_NONTEMPORAL 1
+#endif
+#ifndef EIG3_WAVES_PER_EU
+#define EIG3_WAVES_PER_EU 0
+#endif
+#if EIG3_WAVES_PER_EU > 0
+#define EIG3_KERNEL __global__ __launch_bounds__(kBlock, EIG3_WAVES_PER_EU)
+#else
+#define EIG3_KERNEL __global__ __launch_bounds__(kBlock)
+#endif
+
+template <class T> __device__ __forceinline__ T ld(const T *p)
+{
+#if EIG3_NONTEMPORAL
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <class T> __device__ __forceinline__ void st(T v, T *p)
+{
+#if EIG3_NONTEMPORAL
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 template <class T> struct In9 {
     const T *p[9];
 };
@@ -48,16 +82,47 @@ template <class T, int K> struct AosTile {
     T v[kBlock * kStride];
 };
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <class T> struct Vec16;
+template <> struct Vec16<double> {
+    using type = f64x2;
+    static constexpr int N = 2;
+};
+template <> struct Vec16<float> {
+    using type = f32x4;
+    static constexpr int N = 4;
+};
+
 template <class T, int K>
 __device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t first, int64_t n, AosTile<T, K> &tile)
 {
-    // elements [first*K, min(n, first+kBlock)*K) of base
+    // elements [first*K, min(n, first+kBlock)*K) of base; the span starts at
+    // a multiple of kBlock*K elements, so its 16-byte alignment is that of
+    // base and the branch below is uniform over the grid
     const int64_t m_end = (first + kBlock < n) ? first + kBlock : n;
     const int count = int((m_end - first) * K);
     const T *src = base + first * K;
-    for (int e = threadIdx.x; e < count; e += kBlock) {
+    constexpr int kS = AosTile<T, K>::kStride;
+    int done = 0;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        using V = typename Vec16<T>::type;
+        constexpr int NV = Vec16<T>::N;
+        const int nvec = count / NV;
+        const V *vsrc = reinterpret_cast<const V *>(src);
+        for (int v = threadIdx.x; v < nvec; v += kBlock) {
+            const V x = ld(vsrc + v);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int e = v * NV + j, m = e / K, k = e - m * K;
+                tile.v[m * kS + k] = x[j];
+            }
+        }
+        done = nvec * NV;
+    }
+    for (int e = done + threadIdx.x; e < count; e += kBlock) {
         const int m = e / K, k = e - m * K;
-        tile.v[m * AosTile<T, K>::kStride + k] = __builtin_nontemporal_load(src + e);
+        tile.v[m * kS + k] = ld(src + e);
     }
 }
 
@@ -76,7 +141,7 @@ __device__ __forceinline__ void load_soa(const In9<T> &in, int64_t i, Mat<T, S> 
 {
 #pragma unroll
     for (int k = 0; k < Mat<T, S>::K; ++k)
-        m.a[k] = __builtin_nontemporal_load(in.p[k] + i);
+        m.a[k] = ld(in.p[k] + i);
 }
 
 __device__ __forceinline__ Gen to_gen(const Mat<double, EIG3_GENERAL> &m)
@@ -157,14 +222,14 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
 
 // ------------------------------------------------------------------ kernels
 template <int S, int L, int Acc>
-__global__ __launch_bounds__(kBlock) void k_invariants_f64(int64_t n, In9<double> in, Out4<double> out)
+EIG3_KERNEL void k_invariants_f64(int64_t n, In9<double> in, Out4<double> out)
 {
     for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
         const Inv v = invariants_of<S, Acc>(m);
-        __builtin_nontemporal_store(v.i1, out.p[0] + i);
-        __builtin_nontemporal_store(v.j2, out.p[1] + i);
-        __builtin_nontemporal_store(v.j3, out.p[2] + i);
-        __builtin_nontemporal_store(v.disc, out.p[3] + i);
+        st(v.i1, out.p[0] + i);
+        st(v.j2, out.p[1] + i);
+        st(v.j3, out.p[2] + i);
+        st(v.disc, out.p[3] + i);
     });
 }
 
@@ -172,19 +237,19 @@ template <class T>
 __device__ __forceinline__ void store3(const Out3<T> &out, int layout, int64_t i, T l1, T l2, T l3)
 {
     if (layout == EIG3_SOA) {
-        __builtin_nontemporal_store(l1, out.p[0] + i);
-        __builtin_nontemporal_store(l2, out.p[1] + i);
-        __builtin_nontemporal_store(l3, out.p[2] + i);
+        st(l1, out.p[0] + i);
+        st(l2, out.p[1] + i);
+        st(l3, out.p[2] + i);
     } else {
         T *o = out.p[0] + 3 * i;
-        __builtin_nontemporal_store(l1, o);
-        __builtin_nontemporal_store(l2, o + 1);
-        __builtin_nontemporal_store(l3, o + 2);
+        st(l1, o);
+        st(l2, o + 1);
+        st(l3, o + 2);
     }
 }
 
 template <int S, int L, int OL, int Acc>
-__global__ __launch_bounds__(kBlock) void k_eigvals_f64(int64_t n, In9<double> in, Out3<double> out)
+EIG3_KERNEL void k_eigvals_f64(int64_t n, In9<double> in, Out3<double> out)
 {
     for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
         const Inv v = invariants_of<S, Acc>(m);
@@ -195,19 +260,19 @@ __global__ __launch_bounds__(kBlock) void k_eigvals_f64(int64_t n, In9<double> i
 }
 
 template <int S, int L, int Acc>
-__global__ __launch_bounds__(kBlock) void k_invariants_f32(int64_t n, In9<float> in, Out4<float> out)
+EIG3_KERNEL void k_invariants_f32(int64_t n, In9<float> in, Out4<float> out)
 {
     for_each_matrix<float, S, L>(n, in, [&](int64_t i, const Mat<float, S> &m) {
         const InvW v = invariants_of<S, Acc>(m);
-        __builtin_nontemporal_store(float(v.i1), out.p[0] + i);
-        __builtin_nontemporal_store(float(v.j2), out.p[1] + i);
-        __builtin_nontemporal_store(float(v.j3), out.p[2] + i);
-        __builtin_nontemporal_store(float(v.disc), out.p[3] + i);
+        st(float(v.i1), out.p[0] + i);
+        st(float(v.j2), out.p[1] + i);
+        st(float(v.j3), out.p[2] + i);
+        st(float(v.disc), out.p[3] + i);
     });
 }
 
 template <int S, int L, int OL, int Acc>
-__global__ __launch_bounds__(kBlock) void k_eigvals_f32(int64_t n, In9<float> in, Out3<float> out)
+EIG3_KERNEL void k_eigvals_f32(int64_t n, In9<float> in, Out3<float> out)
 {
     for_each_matrix<float, S, L>(n, in, [&](int64_t i, const Mat<float, S> &m) {
         const InvW v = invariants_of<S, Acc>(m);
@@ -218,18 +283,18 @@ __global__ __launch_bounds__(kBlock) void k_eigvals_f32(int64_t n, In9<float> in
 }
 
 template <int S, int L, int GL, int Acc>
-__global__ __launch_bounds__(kBlock) void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<double> out)
+EIG3_KERNEL void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<double> out)
 {
     for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
         double g1, g2, g3;
         if constexpr (GL == EIG3_SOA) {
-            g1 = __builtin_nontemporal_load(g.p[0] + i);
-            g2 = __builtin_nontemporal_load(g.p[1] + i);
-            g3 = __builtin_nontemporal_load(g.p[2] + i);
+            g1 = ld(g.p[0] + i);
+            g2 = ld(g.p[1] + i);
+            g3 = ld(g.p[2] + i);
         } else {
-            g1 = __builtin_nontemporal_load(g.p[0] + 3 * i);
-            g2 = __builtin_nontemporal_load(g.p[0] + 3 * i + 1);
-            g3 = __builtin_nontemporal_load(g.p[0] + 3 * i + 2);
+            g1 = ld(g.p[0] + 3 * i);
+            g2 = ld(g.p[0] + 3 * i + 1);
+            g3 = ld(g.p[0] + 3 * i + 2);
         }
         const Inv v = invariants_of<S, Acc>(m);
         const Coef c = backward_coefficients(v, g1, g2, g3);
@@ -258,11 +323,11 @@ __global__ __launch_bounds__(kBlock) void k_backward_f64(int64_t n, In9<double> 
         if constexpr (L == EIG3_SOA) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                __builtin_nontemporal_store(o[k], out.p[k] + i);
+                st(o[k], out.p[k] + i);
         } else {
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                __builtin_nontemporal_store(o[k], out.p[0] + K * i + k);
+                st(o[k], out.p[0] + K * i + k);
         }
     });
 }

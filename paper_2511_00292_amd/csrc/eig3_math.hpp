@@ -418,7 +418,7 @@ __device__ __forceinline__ float atan_poly(float u)
     return p;
 }
 
-// atan2(y, x) for y, x >= 0, in [0, pi/2]; atan2(0, 0) = 0.
+// atan2(y, x) for y, x >= 0, in [0, pi/2]; atan2(0, 0) = 0; NaN in, NaN out.
 template <class T> __device__ __forceinline__ T atan2_nonneg(T y, T x)
 {
     const T m = y < x ? y : x;
@@ -426,7 +426,8 @@ template <class T> __device__ __forceinline__ T atan2_nonneg(T y, T x)
     const bool far = m > T(kTanPi8) * M;
     const T num = far ? m - M : m;
     const T den = far ? m + M : M;
-    const T z = M > T(0) ? num / den : T(0);
+    // 0/0 -> 0; a NaN operand fails the comparison and propagates
+    const T z = M == T(0) ? T(0) : num / den;
     T r = z * atan_poly(z * z);
     r = far ? r + T(kPi4) : r;
     return y > x ? T(kPi2) - r : r;
@@ -496,7 +497,8 @@ __device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
     Trig t;
     const double disc = clamp0(v.disc);
     const double j2 = clamp0(v.j2);
-    const double psi = atan2_nonneg(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
+    double psi = atan2_nonneg(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
+    psi = v.j3 == v.j3 ? psi : v.j3; // NaN in J3 reaches the eigenvalues
     sincos_sixth(psi * kThird, t.s, t.c);
     t.r = sqrt(j2 * kThird);
     t.mean = v.i1 * kThird;
@@ -636,7 +638,8 @@ __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float
     const double big = fmax(fmax(y, x), 1e-300);
     const int e = ilogb(big);
     const float yf = float(ldexp(y, -e)), xf = float(ldexp(x, -e));
-    const float psi = atan2_nonneg(yf, xf);
+    float psi = atan2_nonneg(yf, xf);
+    psi = v.j3 == v.j3 ? psi : float(v.j3); // NaN in J3 reaches the eigenvalues
     float s, c;
     sincos_sixth(psi * (1.0f / 3.0f), s, c);
     const float r = sqrtf(float(clamp0(v.j2) * kThird));
