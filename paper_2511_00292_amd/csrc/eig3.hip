@@ -32,6 +32,15 @@ constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 #ifndef EIG3_WAVES_PER_EU
 #define EIG3_WAVES_PER_EU 0
 #endif
+//  EIG3_PIPELINE      1: structure-of-arrays kernels loop over matrices with a
+//                     one-deep register prefetch; the grid is then sized to
+//                     EIG3_BLOCKS_PER_CU workgroups per compute unit
+#ifndef EIG3_PIPELINE
+#define EIG3_PIPELINE 1
+#endif
+#ifndef EIG3_BLOCKS_PER_CU
+#define EIG3_BLOCKS_PER_CU 4
+#endif
 #if EIG3_WAVES_PER_EU > 0
 #define EIG3_KERNEL __global__ __launch_bounds__(kBlock, EIG3_WAVES_PER_EU)
 #else
@@ -176,11 +185,34 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Bod
     constexpr int K = Mat<T, S>::K;
     if constexpr (L == EIG3_SOA) {
         const int64_t stride = int64_t(gridDim.x) * kBlock;
-        for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+#if EIG3_PIPELINE
+        // software pipeline: the loads of the lane's next matrix are issued
+        // before the arithmetic of the current one, so every wave keeps
+        // memory requests in flight while it computes
+        if (i >= n)
+            return;
+        Mat<T, S> cur;
+        load_soa<T, S>(in, i, cur);
+        for (;;) {
+            const int64_t nxt = i + stride;
+            const bool more = nxt < n;
+            Mat<T, S> pre;
+            if (more)
+                load_soa<T, S>(in, nxt, pre);
+            body(i, cur);
+            if (!more)
+                break;
+            cur = pre;
+            i = nxt;
+        }
+#else
+        for (; i < n; i += stride) {
             Mat<T, S> m;
             load_soa<T, S>(in, i, m);
             body(i, m);
         }
+#endif
     } else {
         __shared__ AosTile<T, K> tile;
         const int64_t stride = int64_t(gridDim.x) * kBlock;
@@ -333,10 +365,32 @@ EIG3_KERNEL void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<do
 }
 
 // ------------------------------------------------------------------- host
-int64_t grid_for(int64_t n)
+int device_cus()
+{
+    // compute units of the current device, queried once per device
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+int64_t grid_for(int64_t n, int layout)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
-    return b < kMaxBlocks ? b : kMaxBlocks;
+    int64_t cap = kMaxBlocks;
+#if EIG3_PIPELINE
+    if (layout == EIG3_SOA)
+        cap = int64_t(device_cus()) * EIG3_BLOCKS_PER_CU;
+#endif
+    (void)layout;
+    return b < cap ? b : cap;
 }
 
 bool valid_enum(int v, int hi) { return v >= 0 && v <= hi; }
@@ -469,7 +523,7 @@ int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *
     void *outs[4] = {i1, j2, j3, disc};
     if ((st = check_outputs(A, outs, 4, size_t(A->n))) != EIG3_OK)
         return st;
-    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
     if (A->dtype == EIG3_F32) {
         Out4<float> o32{{static_cast<float *>(i1), static_cast<float *>(j2), static_cast<float *>(j3),
                          static_cast<float *>(disc)}};
@@ -502,7 +556,7 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
     const int nout = out_layout == EIG3_SOA ? 3 : 1;
     if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? 3 : 1))) != EIG3_OK)
         return st;
-    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
     if (A->dtype == EIG3_F32) {
         Out3<float> o32{{static_cast<float *>(outs[0]), static_cast<float *>(outs[1]), static_cast<float *>(outs[2])}};
         const In9<float> in32 = inputs_of<float>(A);
@@ -561,7 +615,7 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
                 return EIG3_EINVAL;
         }
     }
-    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
     const In9<double> in = inputs_of<double>(A);
     G3<double> gg{{static_cast<const double *>(g[0]), static_cast<const double *>(ng == 3 ? g[1] : nullptr),
                    static_cast<const double *>(ng == 3 ? g[2] : nullptr)}};

@@ -116,48 +116,59 @@ struct Gen {
     double a00, a01, a02, a10, a11, a12, a20, a21, a22;
 };
 
-// dx(M; d0, d1, d2) with fused multiply-adds; r[0..13] = r1..r14
-__device__ __forceinline__ void dx_fma(double M01, double M02, double M10, double M12, double M20, double M21,
-                                       double d0, double d1, double d2, double r[14])
+// Off-diagonal entries of M (M = A or A^T) and the diagonal differences of A.
+struct Off {
+    double M01, M02, M10, M12, M20, M21;
+};
+
+// r_(I+1) of dx(M; d0, d1, d2) with fused multiply-adds.
+template <int I> __device__ __forceinline__ double dx_fma_r(const Off &m, double d0, double d1, double d2)
 {
-    const double m01m02 = M01 * M02, m01m12 = M01 * M12, m02m10 = M02 * M10, m02m21 = M02 * M21;
-    const double m01m01 = M01 * M01, m02m02 = M02 * M02, m12m12 = M12 * M12;
-    const double m01m10 = M01 * M10, m02m12 = M02 * M12;
-    r[0] = fma_(m01m12, M20, -(m02m10 * M21));
-    r[1] = fma_(-m01m02, d2, fma_(m01m01, M12, -(m02m02 * M21)));
-    r[2] = fma_(M01 * M21, d1, fma_(-m01m01, M20, m02m21 * M21));
-    r[3] = fma_(m02m12, d0, fma_(m01m12, M12, -(m02m02 * M10)));
-    r[4] = fma_(m01m12, d1, fma_(-m01m02, M10, m02m12 * M21));
-    r[5] = fma_(m02m21, d0, fma_(-m01m02, M20, m01m12 * M21));
-    r[6] = fma_(-m02m10, d2, fma_(m01m10, M12, -(m02m12 * M20)));
-    const double d0d1 = d0 * d1, d1d2 = d1 * d2, d0d2 = d0 * d2;
-    r[7] = fma_(M12, d0d1, fma_(-m02m10, d1, fma_(m01m10, M12, -(m12m12 * M21))));
-    r[8] = fma_(M12, d0d1, fma_(-m02m10, d0, fma_(m02m12, M20, -(m12m12 * M21))));
-    r[9] = fma_(M01, d1d2, fma_(m02m21, d2, fma_(m01m02, M20, -(m01m01 * M10))));
-    r[10] = fma_(M01, d1d2, fma_(m02m21, d1, fma_(m01m12, M21, -(m01m01 * M10))));
-    r[11] = fma_(-M02, d0d2, fma_(m01m12, d0, fma_(m02m12, M21, -(m02m02 * M20))));
-    r[12] = fma_(M02, d0d2, fma_(m01m12, d2, fma_(-m01m02, M10, m02m02 * M20)));
-    r[13] = fma_(d0d1, d2, fma_(-m01m10, d0, fma_(M02 * M20, d1, -(M12 * M21 * d2))));
+    const double M01 = m.M01, M02 = m.M02, M10 = m.M10, M12 = m.M12, M20 = m.M20, M21 = m.M21;
+    if constexpr (I == 0)
+        return fma_(M01 * M12, M20, -(M02 * M10 * M21));
+    else if constexpr (I == 1)
+        return fma_(-(M01 * M02), d2, fma_(M01 * M01, M12, -(M02 * M02 * M21)));
+    else if constexpr (I == 2)
+        return fma_(M01 * M21, d1, fma_(-(M01 * M01), M20, M02 * M21 * M21));
+    else if constexpr (I == 3)
+        return fma_(M02 * M12, d0, fma_(M01 * M12, M12, -(M02 * M02 * M10)));
+    else if constexpr (I == 4)
+        return fma_(M01 * M12, d1, fma_(-(M01 * M02), M10, M02 * M12 * M21));
+    else if constexpr (I == 5)
+        return fma_(M02 * M21, d0, fma_(-(M01 * M02), M20, M01 * M12 * M21));
+    else if constexpr (I == 6)
+        return fma_(-(M02 * M10), d2, fma_(M01 * M10, M12, -(M02 * M12 * M20)));
+    else if constexpr (I == 7)
+        return fma_(M12, d0 * d1, fma_(-(M02 * M10), d1, fma_(M01 * M10, M12, -(M12 * M12 * M21))));
+    else if constexpr (I == 8)
+        return fma_(M12, d0 * d1, fma_(-(M02 * M10), d0, fma_(M02 * M12, M20, -(M12 * M12 * M21))));
+    else if constexpr (I == 9)
+        return fma_(M01, d1 * d2, fma_(M02 * M21, d2, fma_(M01 * M02, M20, -(M01 * M01 * M10))));
+    else if constexpr (I == 10)
+        return fma_(M01, d1 * d2, fma_(M02 * M21, d1, fma_(M01 * M12, M21, -(M01 * M01 * M10))));
+    else if constexpr (I == 11)
+        return fma_(-M02, d0 * d2, fma_(M01 * M12, d0, fma_(M02 * M12, M21, -(M02 * M02 * M20))));
+    else if constexpr (I == 12)
+        return fma_(M02, d0 * d2, fma_(M01 * M12, d2, fma_(-(M01 * M02), M10, M02 * M02 * M20)));
+    else
+        return fma_(d0 * d1, d2, fma_(-(M01 * M10), d0, fma_(M02 * M20, d1, -(M12 * M21 * d2))));
 }
 
-__device__ __forceinline__ double sum_wuv(const double u[14], const double v[14])
+constexpr double kW[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
+
+// Delta = sum_i w_i u_i v_i, u = dx(A), v = dx(A^T), each pair formed and
+// accumulated in turn (small weights first) so that few values stay live.
+template <int I> __device__ __forceinline__ double disc_fma_acc(const Off &a, const Off &at, double d0, double d1,
+                                                                double d2, double s)
 {
-    // w = (9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1); small terms first
-    double s = u[13] * v[13];
-    s = fma_(2.0 * u[12], v[12], s);
-    s = fma_(2.0 * u[11], v[11], s);
-    s = fma_(2.0 * u[10], v[10], s);
-    s = fma_(2.0 * u[9], v[9], s);
-    s = fma_(2.0 * u[8], v[8], s);
-    s = fma_(2.0 * u[7], v[7], s);
-    s = fma_(8.0 * u[6], v[6], s);
-    s = fma_(8.0 * u[5], v[5], s);
-    s = fma_(8.0 * u[4], v[4], s);
-    s = fma_(6.0 * u[3], v[3], s);
-    s = fma_(6.0 * u[2], v[2], s);
-    s = fma_(6.0 * u[1], v[1], s);
-    s = fma_(9.0 * u[0], v[0], s);
-    return s;
+    const double u = dx_fma_r<I>(a, d0, d1, d2);
+    const double v = dx_fma_r<I>(at, d0, d1, d2);
+    s = (I == 13) ? u * v : fma_(kW[I] * u, v, s);
+    if constexpr (I > 0)
+        return disc_fma_acc<I - 1>(a, at, d0, d1, d2, s);
+    else
+        return s;
 }
 
 __device__ __forceinline__ Inv invariants_general_fma(const Gen &A)
@@ -173,11 +184,10 @@ __device__ __forceinline__ Inv invariants_general_fma(const Gen &A)
     const double off3 = fma_(A.a01 * A.a12, A.a20, A.a02 * A.a10 * A.a21);
     const double mixed = fma_(A.a01 * A.a10, t1, fma_(A.a02 * A.a20, t2, A.a12 * A.a21 * t3));
     r.j3 = fma_(-(t1 * t2) * t3, kTwentySeventh, fma_(mixed, kThird, off3));
-    // Delta (Alg. alg:disc-stable)
-    double u[14], v[14];
-    dx_fma(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, u);
-    dx_fma(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, v); // M = A^T
-    r.disc = sum_wuv(u, v);
+    // Delta (Alg. alg:disc-stable); M = A for u, M = A^T for v
+    const Off a{A.a01, A.a02, A.a10, A.a12, A.a20, A.a21};
+    const Off at{A.a10, A.a20, A.a01, A.a21, A.a02, A.a12};
+    r.disc = disc_fma_acc<13>(a, at, g.d0, g.d1, g.d2, 0.0);
     return r;
 }
 
