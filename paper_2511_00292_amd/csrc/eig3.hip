@@ -36,7 +36,7 @@ constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 //                     one-deep register prefetch; the grid is then sized to
 //                     EIG3_BLOCKS_PER_CU workgroups per compute unit
 #ifndef EIG3_PIPELINE
-#define EIG3_PIPELINE 1
+#define EIG3_PIPELINE 0
 #endif
 #ifndef EIG3_BLOCKS_PER_CU
 #define EIG3_BLOCKS_PER_CU 4
