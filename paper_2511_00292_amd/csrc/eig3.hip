@@ -86,7 +86,7 @@ template <class T> struct G3 {
 // (kBlock*K elements) into LDS with 16-byte loads, then each lane reads its K
 // entries.  K = 9 (general) or 6 (symmetric); the LDS row stride K+1 keeps the
 // per-lane reads on distinct banks for K = 9.
-template <class T, int K> struct AosTile {
+template <class T, int K> struct alignas(16) AosTile {
     static constexpr int kStride = (K % 2 == 1) ? K : K + 1;
     T v[kBlock * kStride];
 };
@@ -121,10 +121,15 @@ __device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t fi
         const V *vsrc = reinterpret_cast<const V *>(src);
         for (int v = threadIdx.x; v < nvec; v += kBlock) {
             const V x = ld(vsrc + v);
+            if constexpr (kS == K) {
+                // unpadded rows: the tile is the span itself
+                reinterpret_cast<V *>(tile.v)[v] = x;
+            } else {
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const int e = v * NV + j, m = e / K, k = e - m * K;
-                tile.v[m * kS + k] = x[j];
+                for (int j = 0; j < NV; ++j) {
+                    const int e = v * NV + j, m = e / K, k = e - m * K;
+                    tile.v[m * kS + k] = x[j];
+                }
             }
         }
         done = nvec * NV;

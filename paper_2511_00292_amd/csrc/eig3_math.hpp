@@ -107,6 +107,25 @@ constexpr double kSixth = 1.0 / 6.0;
 constexpr double kThird = 1.0 / 3.0;
 constexpr double kTwentySeventh = 1.0 / 27.0;
 
+// binary64 constants with full mantissas live in the constant address space:
+// the kernels read them with scalar loads into SGPRs, which a VALU operation
+// takes as its scalar operand, instead of rebuilding each one per wave with
+// two vector moves.
+struct ConstTable {
+    double atan[11]; // arctangent polynomial, z^1 .. z^21 (see below)
+    double sinc[7];  // Taylor coefficients of sin, t^3 .. t^15
+    double cosc[7];  // Taylor coefficients of cos, t^2 .. t^14
+};
+__constant__ ConstTable kC = {
+    {0.9999999999999999665383002, -0.3333333333332857960189553, 0.1999999999888207705532328,
+     -0.1428571418297856464657463, 0.1111110625599581821334887, -0.09090774712795826084526493,
+     0.07689975128569665072030238, -0.06640410811535267761156447, 0.05689223501766054343064029,
+     -0.04350445257430010837229732, 0.02116321748124264808858265},
+    {-1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0, 1.0 / 6227020800.0,
+     -1.0 / 1307674368000.0},
+    {-0.5, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0, -1.0 / 3628800.0, 1.0 / 479001600.0, -1.0 / 87178291200.0},
+};
+
 // ====================================================================== FMA
 // The paper's algorithms as printed, with products and sums fused where a
 // fused multiply-add applies.
@@ -402,23 +421,35 @@ constexpr double kPi2 = 1.5707963267948966192;
 constexpr double kPi4 = 0.78539816339744830962;
 constexpr double kTanPi8 = 0.41421356237309504880;
 
-__device__ __forceinline__ double atan_poly(double u)
+// The coefficient tables exist twice: in constant memory (read into SGPRs by
+// scalar loads; used where the kernel has SGPRs to spare) and as immediates
+// (rebuilt in VGPRs; used where the kernel's pointer arguments already fill
+// the SGPR file, i.e. the adjoint with its 21 pointers).
+constexpr double kAtanImm[11] = {0.9999999999999999665383002, -0.3333333333332857960189553,
+                                 0.1999999999888207705532328, -0.1428571418297856464657463,
+                                 0.1111110625599581821334887, -0.09090774712795826084526493,
+                                 0.07689975128569665072030238, -0.06640410811535267761156447,
+                                 0.05689223501766054343064029, -0.04350445257430010837229732,
+                                 0.02116321748124264808858265};
+constexpr double kSinImm[7] = {-1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0,
+                               1.0 / 6227020800.0, -1.0 / 1307674368000.0};
+constexpr double kCosImm[7] = {-0.5, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0, -1.0 / 3628800.0,
+                               1.0 / 479001600.0, -1.0 / 87178291200.0};
+
+template <bool Table> __device__ __forceinline__ double atan_coef(int j) { return Table ? kC.atan[j] : kAtanImm[j]; }
+template <bool Table> __device__ __forceinline__ double sin_coef(int j) { return Table ? kC.sinc[j] : kSinImm[j]; }
+template <bool Table> __device__ __forceinline__ double cos_coef(int j) { return Table ? kC.cosc[j] : kCosImm[j]; }
+
+template <bool Table> __device__ __forceinline__ double atan_poly(double u)
 {
-    double p = 0.02116321748124264808858265;
-    p = fma_(p, u, -0.04350445257430010837229732);
-    p = fma_(p, u, 0.05689223501766054343064029);
-    p = fma_(p, u, -0.06640410811535267761156447);
-    p = fma_(p, u, 0.07689975128569665072030238);
-    p = fma_(p, u, -0.09090774712795826084526493);
-    p = fma_(p, u, 0.1111110625599581821334887);
-    p = fma_(p, u, -0.1428571418297856464657463);
-    p = fma_(p, u, 0.1999999999888207705532328);
-    p = fma_(p, u, -0.3333333333332857960189553);
-    p = fma_(p, u, 0.9999999999999999665383002);
+    double p = atan_coef<Table>(10);
+#pragma unroll
+    for (int j = 9; j >= 0; --j)
+        p = fma_(p, u, atan_coef<Table>(j));
     return p;
 }
 
-__device__ __forceinline__ float atan_poly(float u)
+template <bool Table> __device__ __forceinline__ float atan_poly(float u)
 {
     float p = 0.07984962911065899521160472f;
     p = fma_(p, u, -0.1385147842677151367970504f);
@@ -429,42 +460,48 @@ __device__ __forceinline__ float atan_poly(float u)
 }
 
 // atan2(y, x) for y, x >= 0, in [0, pi/2]; atan2(0, 0) = 0; NaN in, NaN out.
-template <class T> __device__ __forceinline__ T atan2_nonneg(T y, T x)
+template <class T> struct AngleConsts;
+template <> struct AngleConsts<double> {
+    __device__ static double tanpi8() { return kTanPi8; }
+    __device__ static double pi4() { return kPi4; }
+    __device__ static double pi2() { return kPi2; }
+};
+template <> struct AngleConsts<float> {
+    __device__ static float tanpi8() { return float(kTanPi8); }
+    __device__ static float pi4() { return float(kPi4); }
+    __device__ static float pi2() { return float(kPi2); }
+};
+
+template <bool Table = true, class T> __device__ __forceinline__ T atan2_nonneg(T y, T x)
 {
     const T m = y < x ? y : x;
     const T M = y < x ? x : y;
-    const bool far = m > T(kTanPi8) * M;
+    const bool far = m > AngleConsts<T>::tanpi8() * M;
     const T num = far ? m - M : m;
     const T den = far ? m + M : M;
     // 0/0 -> 0; a NaN operand fails the comparison and propagates
     const T z = M == T(0) ? T(0) : num / den;
-    T r = z * atan_poly(z * z);
-    r = far ? r + T(kPi4) : r;
-    return y > x ? T(kPi2) - r : r;
+    T r = z * atan_poly<Table>(z * z);
+    r = far ? r + AngleConsts<T>::pi4() : r;
+    return y > x ? AngleConsts<T>::pi2() - r : r;
 }
 
-__device__ __forceinline__ void sincos_sixth(double t, double &s, double &c)
+template <bool Table> __device__ __forceinline__ void sincos_sixth(double t, double &s, double &c)
 {
     const double u = t * t;
-    double ps = -1.0 / 1307674368000.0;
-    ps = fma_(ps, u, 1.0 / 6227020800.0);
-    ps = fma_(ps, u, -1.0 / 39916800.0);
-    ps = fma_(ps, u, 1.0 / 362880.0);
-    ps = fma_(ps, u, -1.0 / 5040.0);
-    ps = fma_(ps, u, 1.0 / 120.0);
-    ps = fma_(ps, u, -1.0 / 6.0);
+    double ps = sin_coef<Table>(6);
+#pragma unroll
+    for (int j = 5; j >= 0; --j)
+        ps = fma_(ps, u, sin_coef<Table>(j));
     s = fma_(t * u, ps, t);
-    double pc = -1.0 / 87178291200.0;
-    pc = fma_(pc, u, 1.0 / 479001600.0);
-    pc = fma_(pc, u, -1.0 / 3628800.0);
-    pc = fma_(pc, u, 1.0 / 40320.0);
-    pc = fma_(pc, u, -1.0 / 720.0);
-    pc = fma_(pc, u, 1.0 / 24.0);
-    pc = fma_(pc, u, -0.5);
+    double pc = cos_coef<Table>(6);
+#pragma unroll
+    for (int j = 5; j >= 0; --j)
+        pc = fma_(pc, u, cos_coef<Table>(j));
     c = fma_(u, pc, 1.0);
 }
 
-__device__ __forceinline__ void sincos_sixth(float t, float &s, float &c)
+template <bool Table> __device__ __forceinline__ void sincos_sixth(float t, float &s, float &c)
 {
     const float u = t * t;
     float ps = 1.0f / 362880.0f;
@@ -502,14 +539,14 @@ constexpr double kSqrt3 = 1.7320508075688772935;
 // max(x, 0) that keeps NaN (fmax would drop it)
 __device__ __forceinline__ double clamp0(double x) { return x < 0.0 ? 0.0 : x; }
 
-__device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
+template <bool Table = true> __device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
 {
     Trig t;
     const double disc = clamp0(v.disc);
     const double j2 = clamp0(v.j2);
-    double psi = atan2_nonneg(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
+    double psi = atan2_nonneg<Table>(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
     psi = v.j3 == v.j3 ? psi : v.j3; // NaN in J3 reaches the eigenvalues
-    sincos_sixth(psi * kThird, t.s, t.c);
+    sincos_sixth<Table>(psi * kThird, t.s, t.c);
     t.r = sqrt(j2 * kThird);
     t.mean = v.i1 * kThird;
     t.neg = v.j3 < 0.0;
@@ -648,10 +685,10 @@ __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float
     const double big = fmax(fmax(y, x), 1e-300);
     const int e = ilogb(big);
     const float yf = float(ldexp(y, -e)), xf = float(ldexp(x, -e));
-    float psi = atan2_nonneg(yf, xf);
+    float psi = atan2_nonneg<false>(yf, xf);
     psi = v.j3 == v.j3 ? psi : float(v.j3); // NaN in J3 reaches the eigenvalues
     float s, c;
-    sincos_sixth(psi * (1.0f / 3.0f), s, c);
+    sincos_sixth<false>(psi * (1.0f / 3.0f), s, c);
     const float r = sqrtf(float(clamp0(v.j2) * kThird));
     const float mean = float(v.i1 * kThird);
     const float a1 = -r * fma_(float(kSqrt3), s, c);
@@ -678,7 +715,7 @@ struct Coef {
 
 __device__ __forceinline__ Coef backward_coefficients(const Inv &v, double g1, double g2, double g3)
 {
-    const Trig t = trig_from_invariants(v);
+    const Trig t = trig_from_invariants<false>(v);
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
     // gaps of the |J3| configuration; for J3 < 0 they swap roles
