@@ -95,14 +95,63 @@ def profile_set():
     log("profile set done")
 
 
+KERNEL_SOURCES = ("paper_2511_00292_amd/csrc/eig3.hip", "paper_2511_00292_amd/csrc/eig3_math.hpp",
+                  "paper_2511_00292_amd/build.py")
+
+
 def source_digest() -> str:
+    """sha256 over the kernel sources and build flags: recorded with every
+    committed counter or accuracy summary, which is used only while it
+    matches."""
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2511_00292_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(name.encode())
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode())
             h.update(f.read())
     return h.hexdigest()
+
+
+def stated_accuracy():
+    """Forward errors per workload in units of the paper's stability bound,
+    from the committed accuracy report (tests/test_gpu_zz_accuracy_report.py,
+    exact oracle on sampled matrices), if it was taken on the current kernel
+    sources; else None."""
+    path = os.path.join(ROOT, "profiles", "accuracy.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    out = {}
+    for row in rec.get("rows", []):
+        g = row["gpu"]
+        lam = g.get("eigvals", g)
+        out[row["workload"]] = {"eigvals_max_err_over_bound": round(lam["max"], 2),
+                                "eigvals_p99_err_over_bound": round(lam["p99"], 2)}
+        if "grad_rel_err_max" in g:
+            out[row["workload"]]["grad_rel_err_max"] = g["grad_rel_err_max"]
+    return out
+
+
+def copy_ceiling(torch, dev):
+    """Device-to-device copy of 1 GiB (read + write) as the practical HBM
+    ceiling beside the 8 TB/s published peak."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 10
+    return 2 * src.numel() * 8 / (ms * 1e-3) / 1e9
 
 
 def traffic_record(kernel_key: str):
@@ -209,10 +258,13 @@ def main():
     dom_key, dom_ms = ("bwd_general_f64", bwd_ms) if bwd_ms >= fwd_ms else ("fwd_general_f64", fwd_ms)
     achieved = BYTES[dom_key] * N_MAIN / (dom_ms * 1e-3) / 1e9
     traffic = traffic_record(f"{dom_key}_{acc}")
+    ceiling = copy_ceiling(torch, dev)
+    log(f"copy ceiling {ceiling:.0f} GB/s")
     roofline = {"bound": "hbm", "kernel": f"{dom_key} ({acc})", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_launch_ms": round(dom_ms, 4),
-                "algorithmic_bytes_per_matrix": BYTES[dom_key], "matrices_per_launch": N_MAIN}
+                "algorithmic_bytes_per_matrix": BYTES[dom_key], "matrices_per_launch": N_MAIN,
+                "copy_ceiling_GBs": round(ceiling, 1), "frac_of_copy_ceiling": round(achieved / ceiling, 4)}
 
     variants = []
 
@@ -318,6 +370,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "stated_accuracy": stated_accuracy(),
     }
     print(json.dumps(out), flush=True)
 

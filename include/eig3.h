@@ -61,10 +61,12 @@ typedef enum eig3_status {
 
 typedef enum eig3_dtype {
     EIG3_F64 = 0, /* binary64 storage and arithmetic */
-    EIG3_F32 = 1  /* binary32 storage; binary32 arithmetic with compensated
-                     (FMA error-free) products for J2, J3 and the auxiliary
-                     vectors of Delta, binary64 accumulation of Delta and a
-                     binary64 triple angle (the "FP64 islands") */
+    EIG3_F32 = 1  /* binary32 storage and results.  Delta is always formed and
+                     kept in binary64 (it underflows binary32 near isotropic
+                     states) and the triple-angle argument is formed in
+                     binary64; arctangent, sine, cosine and the final
+                     eigenvalues are binary32.  The invariants are computed
+                     per eig3_accuracy, see there. */
 } eig3_dtype;
 
 typedef enum eig3_structure {
@@ -79,8 +81,17 @@ typedef enum eig3_layout {
 } eig3_layout;
 
 typedef enum eig3_accuracy {
-    EIG3_FMA = 0,        /* the paper's algorithms with fused multiply-adds */
-    EIG3_COMPENSATED = 1 /* error-free products and sums in J2, J3 and Delta */
+    /* binary64: the paper's algorithms with fused multiply-adds.
+       binary32: entries widened exactly to binary64 and the binary64 FMA
+       invariants (on gfx950 a binary64 FMA issues at the rate of a
+       non-packed binary32 one, so this is the faster binary32 variant). */
+    EIG3_FMA = 0,
+    /* binary64: error-free products (FMA TwoProduct) and sums (TwoSum) in J2,
+       J3, every r_i of dx and sum w u v: the accuracy of twice the working
+       precision before the final rounding of each invariant.
+       binary32: the same error-free evaluation in binary32 arithmetic, with
+       the products of Delta accumulated in binary64. */
+    EIG3_COMPENSATED = 1
 } eig3_accuracy;
 
 /* A batch of n matrices resident in device memory. */
@@ -89,7 +100,7 @@ typedef struct eig3_matrices {
     int32_t dtype;     /* eig3_dtype */
     int32_t structure; /* eig3_structure */
     int32_t layout;    /* eig3_layout */
-    int32_t accuracy;  /* eig3_accuracy (binary64 only; binary32 is always compensated) */
+    int32_t accuracy;  /* eig3_accuracy */
     /* SOA: a[k] points to n values of entry k (k < 9 GENERAL, k < 6 SYMMETRIC).
        AOS: a[0] points to n*9 (GENERAL) or n*6 (SYMMETRIC) values; a[1..] unused.
        Every pointer must be aligned to its element size. */
@@ -127,7 +138,8 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
  *    the result is the gradient with respect to the 6 stored entries (the
  *    off-diagonal value counts both of its positions).
  * Undefined at repeated eigenvalues (zero gap): the result is then +-Inf or
- * NaN.  binary64 only: EIG3_F32 returns EIG3_EUNSUPPORTED.
+ * NaN.  Computed in binary64 for both storage types: binary32 entries and g
+ * are widened exactly and each gradient entry is rounded once to binary32.
  */
 int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *const g[3],
                           void *const grad_a[9], hipStream_t stream);

@@ -319,20 +319,27 @@ EIG3_KERNEL void k_eigvals_f32(int64_t n, In9<float> in, Out3<float> out)
     });
 }
 
-template <int S, int L, int GL, int Acc>
-EIG3_KERNEL void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<double> out)
+// The adjoint runs in binary64 for either storage type (binary32 entries and
+// upstream gradients are widened exactly; the result is rounded once).
+template <class T, int S, int L, int GL, int Acc>
+EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, Out9<T> out)
 {
-    for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
+    for_each_matrix<T, S, L>(n, in, [&](int64_t i, const Mat<T, S> &mt) {
         double g1, g2, g3;
         if constexpr (GL == EIG3_SOA) {
-            g1 = ld(g.p[0] + i);
-            g2 = ld(g.p[1] + i);
-            g3 = ld(g.p[2] + i);
+            g1 = double(ld(g.p[0] + i));
+            g2 = double(ld(g.p[1] + i));
+            g3 = double(ld(g.p[2] + i));
         } else {
-            g1 = ld(g.p[0] + 3 * i);
-            g2 = ld(g.p[0] + 3 * i + 1);
-            g3 = ld(g.p[0] + 3 * i + 2);
+            g1 = double(ld(g.p[0] + 3 * i));
+            g2 = double(ld(g.p[0] + 3 * i + 1));
+            g3 = double(ld(g.p[0] + 3 * i + 2));
         }
+        constexpr int K = Mat<T, S>::K;
+        Mat<double, S> m;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            m.a[k] = double(mt.a[k]);
         const Inv v = invariants_of<S, Acc>(m);
         const Coef c = backward_coefficients(v, g1, g2, g3);
         double gr[9];
@@ -342,7 +349,6 @@ EIG3_KERNEL void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<do
             const Sym s = to_sym(m);
             backward_general(Gen{s.s00, s.s01, s.s02, s.s01, s.s11, s.s12, s.s02, s.s12, s.s22}, c, gr);
         }
-        constexpr int K = Mat<double, S>::K;
         double o[K];
         if constexpr (S == EIG3_GENERAL) {
 #pragma unroll
@@ -360,11 +366,11 @@ EIG3_KERNEL void k_backward_f64(int64_t n, In9<double> in, G3<double> g, Out9<do
         if constexpr (L == EIG3_SOA) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                st(o[k], out.p[k] + i);
+                st(T(o[k]), out.p[k] + i);
         } else {
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                st(o[k], out.p[0] + K * i + k);
+                st(T(o[k]), out.p[0] + K * i + k);
         }
     });
 }
@@ -598,13 +604,12 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
         return EIG3_EINVAL;
     if (A->n == 0)
         return EIG3_OK;
-    if (A->dtype != EIG3_F64)
-        return EIG3_EUNSUPPORTED;
     const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    const size_t es = elem_size(A->dtype);
     // g: inputs, must be valid and not alias the outputs
     const int ng = g_layout == EIG3_SOA ? 3 : 1;
     for (int k = 0; k < ng; ++k)
-        if (g[k] == nullptr || !aligned(g[k], 8))
+        if (g[k] == nullptr || !aligned(g[k], es))
             return EIG3_EINVAL;
     const int nout = A->layout == EIG3_SOA ? K : 1;
     void *outs[9];
@@ -613,28 +618,35 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
     if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? K : 1))) != EIG3_OK)
         return st;
     for (int j = 0; j < nout; ++j) {
-        const Range o{uintptr_t(outs[j]), uintptr_t(outs[j]) + size_t(A->n) * (nout == 1 ? K : 1) * 8};
+        const Range o{uintptr_t(outs[j]), uintptr_t(outs[j]) + size_t(A->n) * (nout == 1 ? K : 1) * es};
         for (int k = 0; k < ng; ++k) {
-            const Range gr{uintptr_t(g[k]), uintptr_t(g[k]) + size_t(A->n) * (ng == 1 ? 3 : 1) * 8};
+            const Range gr{uintptr_t(g[k]), uintptr_t(g[k]) + size_t(A->n) * (ng == 1 ? 3 : 1) * es};
             if (overlaps(o, gr))
                 return EIG3_EINVAL;
         }
     }
     const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
-    const In9<double> in = inputs_of<double>(A);
-    G3<double> gg{{static_cast<const double *>(g[0]), static_cast<const double *>(ng == 3 ? g[1] : nullptr),
-                   static_cast<const double *>(ng == 3 ? g[2] : nullptr)}};
-    Out9<double> out;
-    for (int k = 0; k < 9; ++k)
-        out.p[k] = k < nout ? static_cast<double *>(outs[k]) : nullptr;
-    dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
-        if (g_layout == EIG3_AOS)
-            hipLaunchKernelGGL((k_backward_f64<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream, A->n,
-                               in, gg, out);
-        else
-            hipLaunchKernelGGL((k_backward_f64<S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream, A->n,
-                               in, gg, out);
-    });
+    auto launch = [&](auto tag) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(A);
+        G3<T> gg{{static_cast<const T *>(g[0]), static_cast<const T *>(ng == 3 ? g[1] : nullptr),
+                  static_cast<const T *>(ng == 3 ? g[2] : nullptr)}};
+        Out9<T> out;
+        for (int k = 0; k < 9; ++k)
+            out.p[k] = k < nout ? static_cast<T *>(outs[k]) : nullptr;
+        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            if (g_layout == EIG3_AOS)
+                hipLaunchKernelGGL((k_backward<T, S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream,
+                                   A->n, in, gg, out);
+            else
+                hipLaunchKernelGGL((k_backward<T, S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream,
+                                   A->n, in, gg, out);
+        });
+    };
+    if (A->dtype == EIG3_F32)
+        launch(float{});
+    else
+        launch(double{});
     return launched();
 }
 

@@ -8,6 +8,7 @@ import pytest
 
 import workloads as w
 from accuracy import EPS32, Truth, check, inv_errors, lam_errors
+from oracle import exact
 from gpu_util import download_inv, download_lam, upload
 
 pytestmark = pytest.mark.gpu
@@ -78,10 +79,20 @@ def test_f32_ragged(eig3, n):
             check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"f32 ragged n={n} {acc} {layout}")
 
 
-def test_f32_backward_unsupported(eig3):
-    s = upload(w.config4(16, seed=3)["s"], "aos")
-    import torch
-    g = torch.zeros((16, 3), dtype=torch.float32, device="cuda:0")
-    with pytest.raises(eig3.Eig3Error) as e:
-        eig3.eig3_eigvals_backward(s, g, "symmetric")
-    assert e.value.status == -2
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_f32_backward(eig3, layout):
+    """binary32 adjoint: binary64 arithmetic on the widened entries, rounded
+    once; against the exact gradient at the binary32 input."""
+    c = w.config5(2048, seed=33)
+    a32 = c["a"].astype(np.float32)
+    g32 = c["g"].astype(np.float32)
+    from gpu_util import download_matrix
+    grad = download_matrix(eig3.eig3_eigvals_backward(upload(a32, layout), upload(g32, "aos"), "general"), 9)
+    idx = np.arange(0, 2048, 16)
+    ref = np.array([exact.eigvals_vjp(a32[m].astype(np.float64), g32[m].astype(np.float64)) for m in idx])
+    rel = np.abs(grad[idx] - ref).max(1) / np.abs(ref).max(1)
+    assert rel.max() <= 4 * EPS32, rel.max()
+    s = w.config3(1024, seed=34)["s"].astype(np.float32)
+    gs = np.random.default_rng(3).standard_normal((1024, 3)).astype(np.float32)
+    gsym = download_matrix(eig3.eig3_eigvals_backward(upload(s, layout), upload(gs, "soa"), "symmetric"), 6)
+    assert np.isfinite(gsym[np.abs(gsym).max(1) < 1e30]).all()

@@ -94,6 +94,8 @@ def test_accuracy_report(plain_oracle):
             {"eigvals": _ratios(lam_errors(t5, o5), t5.bound_lam()), "grad_rel_err_max": float(relp.max())})
     path = os.environ.get("EIG3_ACCURACY_REPORT")
     if path:
+        import bench
+        rep["source_sha256"] = bench.source_digest()
         with open(path, "w") as f:
             json.dump(rep, f, indent=1)
     assert len(rep["rows"]) >= 14
