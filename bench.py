@@ -136,22 +136,26 @@ def stated_accuracy():
 
 
 def copy_ceiling(torch, dev):
-    """Device-to-device copy of 1 GiB (read + write) as the practical HBM
-    ceiling beside the 8 TB/s published peak."""
+    """Best of two plain 1 GiB device copies (runtime copy and an elementwise
+    kernel; 1 GiB read + 1 GiB written) as the practical HBM ceiling beside
+    the 8 TB/s published peak."""
     src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(10):
-        dst.copy_(src)
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / 10
-    return 2 * src.numel() * 8 / (ms * 1e-3) / 1e9
+    best = 0.0
+    for fn in (lambda: dst.copy_(src), lambda: torch.mul(src, 1.0, out=dst)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(10):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / 10
+        best = max(best, 2 * src.numel() * 8 / (ms * 1e-3) / 1e9)
+    return best
 
 
 def traffic_record(kernel_key: str):

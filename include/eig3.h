@@ -91,7 +91,15 @@ typedef enum eig3_accuracy {
        precision before the final rounding of each invariant.
        binary32: the same error-free evaluation in binary32 arithmetic, with
        the products of Delta accumulated in binary64. */
-    EIG3_COMPENSATED = 1
+    EIG3_COMPENSATED = 1,
+    /* Comparators (binary64 eig3_invariants / eig3_eigvals only; other calls
+       return EIG3_EUNSUPPORTED): the paper's naive evaluations in plain
+       binary64, Delta = 4 J2^3 - 27 J3^2 from them.
+       NAIVE: monomial sums, Alg. alg:J2-naive and alg:J3-naive.
+       NAIVE_TENSOR: S = A - tr(A)/3 I, J2 = tr(S S)/2, J3 = det S by LU with
+       partial pivoting, Alg. alg:J2-tensor and alg:J3-tensor. */
+    EIG3_NAIVE = 2,
+    EIG3_NAIVE_TENSOR = 3
 } eig3_accuracy;
 
 /* A batch of n matrices resident in device memory. */

@@ -113,6 +113,94 @@ static double alg_disc(const double *A)
     return disc;
 }
 
+/* ------------------------------------------------- comparators (naive) */
+/* Alg. alg:J2-naive: the unrolled monomial sum, evaluated left to right. */
+static double alg_J2_naive(const double *A)
+{
+    const double A00 = A[0], A01 = A[1], A02 = A[2];
+    const double A10 = A[3], A11 = A[4], A12 = A[5];
+    const double A20 = A[6], A21 = A[7], A22 = A[8];
+    return (A00 * A00 - A00 * A11 - A00 * A22 + 3 * A01 * A10 + 3 * A02 * A20 + A11 * A11 - A11 * A22 +
+            3 * A12 * A21 + A22 * A22) / 3.0;
+}
+
+/* Alg. alg:J3-naive: the unrolled monomial sum, evaluated left to right. */
+static double alg_J3_naive(const double *A)
+{
+    const double A00 = A[0], A01 = A[1], A02 = A[2];
+    const double A10 = A[3], A11 = A[4], A12 = A[5];
+    const double A20 = A[6], A21 = A[7], A22 = A[8];
+    return (2 * A00 * A00 * A00 - 3 * A00 * A00 * A11 - 3 * A00 * A00 * A22 + 9 * A00 * A01 * A10 +
+            9 * A00 * A02 * A20 - 3 * A00 * A11 * A11 + 12 * A00 * A11 * A22 - 18 * A00 * A12 * A21 -
+            3 * A00 * A22 * A22 + 9 * A01 * A10 * A11 - 18 * A01 * A10 * A22 + 27 * A01 * A12 * A20 +
+            27 * A02 * A10 * A21 - 18 * A02 * A11 * A20 + 9 * A02 * A20 * A22 + 2 * A11 * A11 * A11 -
+            3 * A11 * A11 * A22 + 9 * A11 * A12 * A21 - 3 * A11 * A22 * A22 + 9 * A12 * A21 * A22 +
+            2 * A22 * A22 * A22) / 27.0;
+}
+
+/* Alg. alg:J2-tensor / alg:J3-tensor: S = A - tr(A)/3 I, then tr(S S)/2 and
+   det S, the determinant by LU with partial pivoting (row operations with
+   the reciprocal of the pivot, as the LAPACK factorisation used by NumPy's
+   determinant does). */
+static void tensor_dev(const double *A, double *S)
+{
+    double mean = (A[0] + A[4] + A[8]) / 3.0;
+    for (int e = 0; e < 9; ++e)
+        S[e] = A[e];
+    S[0] -= mean;
+    S[4] -= mean;
+    S[8] -= mean;
+}
+
+static double alg_J2_tensor(const double *A)
+{
+    double S[9];
+    tensor_dev(A, S);
+    double tr = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double sii = 0.0;
+        for (int k = 0; k < 3; ++k)
+            sii = sii + S[3 * i + k] * S[3 * k + i];
+        tr = tr + sii;
+    }
+    return tr / 2.0;
+}
+
+static double det_lu(double *M)
+{
+    double sign = 1.0;
+    for (int c = 0; c < 2; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(M[3 * r + c]) > fabs(M[3 * p + c]))
+                p = r;
+        if (p != c) {
+            for (int k = 0; k < 3; ++k) {
+                double t = M[3 * c + k];
+                M[3 * c + k] = M[3 * p + k];
+                M[3 * p + k] = t;
+            }
+            sign = -sign;
+        }
+        if (M[3 * c + c] != 0.0) {
+            double inv = 1.0 / M[3 * c + c];
+            for (int r = c + 1; r < 3; ++r) {
+                double l = M[3 * r + c] * inv;
+                for (int k = c + 1; k < 3; ++k)
+                    M[3 * r + k] = M[3 * r + k] - l * M[3 * c + k];
+            }
+        }
+    }
+    return sign * (M[0] * M[4] * M[8]);
+}
+
+static double alg_J3_tensor(const double *A)
+{
+    double S[9];
+    tensor_dev(A, S);
+    return det_lu(S);
+}
+
 /* ---------------------------------------------------------------- Alg. 9 */
 static void alg_eigvals(double I1, double J2, double J3, double disc, double *lam)
 {
@@ -134,6 +222,18 @@ static void alg_eigvals(double I1, double J2, double J3, double disc, double *la
 static void one_eigvals(const double *A, double *lam)
 {
     alg_eigvals(alg_I1(A), alg_J2(A), alg_J3(A), alg_disc(A), lam);
+}
+
+/* naive comparators: variant 1 = Alg. alg:J2-naive / alg:J3-naive,
+   variant 2 = Alg. alg:J2-tensor / alg:J3-tensor; Delta = 4 J2^3 - 27 J3^2 */
+static void one_invariants_naive(const double *A, int variant, double *out)
+{
+    double j2 = variant == 1 ? alg_J2_naive(A) : alg_J2_tensor(A);
+    double j3 = variant == 1 ? alg_J3_naive(A) : alg_J3_tensor(A);
+    out[0] = alg_I1(A);
+    out[1] = j2;
+    out[2] = j3;
+    out[3] = 4.0 * j2 * j2 * j2 - 27.0 * j3 * j3;
 }
 
 /* -------------------------------------------------- backward, E_k route */
@@ -206,6 +306,17 @@ EXPORT void oracle_aux_vectors(const double *A, double *u, double *v)
     double d0 = A[0] - A[4], d1 = A[0] - A[8], d2 = A[4] - A[8];
     alg_dx(A, d0, d1, d2, u);
     alg_dx(At, d0, d1, d2, v);
+}
+
+/* naive comparators (variant 1: monomial sums, 2: tensor) -- invariants
+   out[n*4] = (I1, J2, J3, Delta) and eigenvalues lam[n*3] */
+EXPORT void oracle_naive(int64_t n, const double *a, int variant, double *inv, double *lam)
+{
+    for (int64_t m = 0; m < n; ++m) {
+        double *o = inv + 4 * m;
+        one_invariants_naive(a + 9 * m, variant, o);
+        alg_eigvals(o[0], o[1], o[2], o[3], lam + 3 * m);
+    }
 }
 
 /* eigenvalues, ascending: lam[n*3] */

@@ -35,6 +35,7 @@ class PlainOracle:
         lib.oracle_eigvals_from_invariants.argtypes = [i64, _D, _D, _D, _D, _D]
         lib.oracle_eigvals_backward.argtypes = [i64, _D, _D, _D, i32]
         lib.oracle_aux_vectors.argtypes = [_D, _D, _D]
+        lib.oracle_naive.argtypes = [i64, _D, i32, _D, _D]
         lib.oracle_max_threads.restype = ctypes.c_int
         self.lib = lib
         self.path = lib_path
@@ -74,6 +75,19 @@ class PlainOracle:
         grad = np.empty_like(a)
         self.lib.oracle_eigvals_backward(a.shape[0], _p(a), _p(g), _p(grad), threads)
         return grad
+
+    def naive(self, a, variant: str):
+        """The paper's comparators: variant "naive" (Alg. alg:J2-naive,
+        alg:J3-naive) or "tensor" (Alg. alg:J2-tensor, alg:J3-tensor), with
+        Delta = 4 J2^3 - 27 J3^2 and Alg. alg:eigvals-stable.  Returns
+        (invariants (n, 4), eigenvalues (n, 3))."""
+        a = _mat(a)
+        n = a.shape[0]
+        inv = np.empty((n, 4))
+        lam = np.empty((n, 3))
+        v = {"naive": 1, "tensor": 2}[variant]
+        self.lib.oracle_naive(n, _p(a), v, _p(inv), _p(lam))
+        return inv, lam
 
     def aux_vectors(self, a9):
         """u = dx(A), v = dx(A^T) of one matrix (Alg. alg:disc-stable)."""
@@ -117,3 +131,7 @@ def eigvals_backward(a, g, threads: int = 0):
 
 def aux_vectors(a9):
     return _load().aux_vectors(a9)
+
+
+def naive(a, variant: str):
+    return _load().naive(a, variant)

@@ -20,8 +20,8 @@ from typing import Sequence, Union
 import torch
 
 from . import _capi
-from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EIG3_GENERAL, EIG3_SOA,
-                    EIG3_SYMMETRIC, Eig3Error)
+from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EIG3_GENERAL, EIG3_NAIVE,
+                    EIG3_NAIVE_TENSOR, EIG3_SOA, EIG3_SYMMETRIC, Eig3Error)
 
 __all__ = [
     "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eigvals", "Eig3Eigvals",
@@ -34,7 +34,7 @@ ENTRIES = {
 }
 
 _STRUCT = {"general": EIG3_GENERAL, "symmetric": EIG3_SYMMETRIC}
-_ACC = {"fma": EIG3_FMA, "compensated": EIG3_COMPENSATED}
+_ACC = {"fma": EIG3_FMA, "compensated": EIG3_COMPENSATED, "naive": EIG3_NAIVE, "naive_tensor": EIG3_NAIVE_TENSOR}
 _DTYPE = {torch.float64: EIG3_F64, torch.float32: EIG3_F32}
 
 Batch = Union[torch.Tensor, Sequence[torch.Tensor]]

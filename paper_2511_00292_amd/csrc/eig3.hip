@@ -169,7 +169,19 @@ __device__ __forceinline__ Sym to_sym(const Mat<double, EIG3_SYMMETRIC> &m)
 
 template <int S, int Acc> __device__ __forceinline__ Inv invariants_of(const Mat<double, S> &m)
 {
-    if constexpr (S == EIG3_GENERAL) {
+    if constexpr (Acc == EIG3_NAIVE || Acc == EIG3_NAIVE_TENSOR) {
+        Gen g;
+        if constexpr (S == EIG3_GENERAL) {
+            g = to_gen(m);
+        } else {
+            const Sym y = to_sym(m);
+            g = Gen{y.s00, y.s01, y.s02, y.s01, y.s11, y.s12, y.s02, y.s12, y.s22};
+        }
+        if constexpr (Acc == EIG3_NAIVE)
+            return invariants_general_naive(g);
+        else
+            return invariants_general_tensor(g);
+    } else if constexpr (S == EIG3_GENERAL) {
         if constexpr (Acc == EIG3_COMPENSATED)
             return invariants_general_comp(to_gen(m));
         else
@@ -436,7 +448,7 @@ int check_matrices(const eig3_matrices *A)
     if (A == nullptr || A->n < 0)
         return EIG3_EINVAL;
     if (!valid_enum(A->dtype, 1) || !valid_enum(A->structure, 1) || !valid_enum(A->layout, 1) ||
-        !valid_enum(A->accuracy, 1))
+        !valid_enum(A->accuracy, 3))
         return EIG3_EINVAL;
     if (A->n == 0)
         return EIG3_OK;
@@ -503,6 +515,33 @@ template <class F> void dispatch_sla(int s, int l, int acc, F f)
         b(std::integral_constant<int, EIG3_GENERAL>{});
 }
 
+// the same with the two comparator modes (binary64 forward kernels only)
+template <class F> void dispatch_sla4(int s, int l, int acc, F f)
+{
+    if (acc == EIG3_NAIVE || acc == EIG3_NAIVE_TENSOR) {
+        auto a = [&](auto S, auto L) {
+            if (acc == EIG3_NAIVE)
+                f(S, L, std::integral_constant<int, EIG3_NAIVE>{});
+            else
+                f(S, L, std::integral_constant<int, EIG3_NAIVE_TENSOR>{});
+        };
+        auto b = [&](auto S) {
+            if (l == EIG3_AOS)
+                a(S, std::integral_constant<int, EIG3_AOS>{});
+            else
+                a(S, std::integral_constant<int, EIG3_SOA>{});
+        };
+        if (s == EIG3_SYMMETRIC)
+            b(std::integral_constant<int, EIG3_SYMMETRIC>{});
+        else
+            b(std::integral_constant<int, EIG3_GENERAL>{});
+        return;
+    }
+    dispatch_sla(s, l, acc, f);
+}
+
+bool comparator(int acc) { return acc == EIG3_NAIVE || acc == EIG3_NAIVE_TENSOR; }
+
 } // namespace
 
 // ===================================================================== C ABI
@@ -536,6 +575,8 @@ int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *
         return st;
     const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
     if (A->dtype == EIG3_F32) {
+        if (comparator(A->accuracy))
+            return EIG3_EUNSUPPORTED;
         Out4<float> o32{{static_cast<float *>(i1), static_cast<float *>(j2), static_cast<float *>(j3),
                          static_cast<float *>(disc)}};
         const In9<float> in32 = inputs_of<float>(A);
@@ -548,7 +589,7 @@ int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *
     Out4<double> out{{static_cast<double *>(i1), static_cast<double *>(j2), static_cast<double *>(j3),
                       static_cast<double *>(disc)}};
     const In9<double> in = inputs_of<double>(A);
-    dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+    dispatch_sla4(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
         hipLaunchKernelGGL((k_invariants_f64<S.value, L.value, Acc.value>), grid, block, 0, stream, A->n, in, out);
     });
     return launched();
@@ -569,6 +610,8 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
         return st;
     const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
     if (A->dtype == EIG3_F32) {
+        if (comparator(A->accuracy))
+            return EIG3_EUNSUPPORTED;
         Out3<float> o32{{static_cast<float *>(outs[0]), static_cast<float *>(outs[1]), static_cast<float *>(outs[2])}};
         const In9<float> in32 = inputs_of<float>(A);
         dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
@@ -583,7 +626,7 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
     }
     Out3<double> out{{static_cast<double *>(outs[0]), static_cast<double *>(outs[1]), static_cast<double *>(outs[2])}};
     const In9<double> in = inputs_of<double>(A);
-    dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+    dispatch_sla4(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
         if (out_layout == EIG3_AOS)
             hipLaunchKernelGGL((k_eigvals_f64<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream, A->n,
                                in, out);
@@ -604,6 +647,8 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
         return EIG3_EINVAL;
     if (A->n == 0)
         return EIG3_OK;
+    if (comparator(A->accuracy))
+        return EIG3_EUNSUPPORTED;
     const int K = A->structure == EIG3_GENERAL ? 9 : 6;
     const size_t es = elem_size(A->dtype);
     // g: inputs, must be valid and not alias the outputs

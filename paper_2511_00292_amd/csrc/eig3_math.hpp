@@ -573,6 +573,94 @@ __device__ __forceinline__ void eigvals_from_invariants(const Inv &v, double &l1
     l3 = t.mean + m3;
 }
 
+// ============================================================ comparators
+// The paper's naive evaluations, kept as GPU comparators that show why the
+// stable algorithms are needed.  Plain products and sums, no FMA, in the
+// printed (left-to-right) order, so that they reproduce a plain binary64
+// evaluation operation for operation.
+//   naive:  Alg. alg:J2-naive and alg:J3-naive (monomial sums)
+//   tensor: Alg. alg:J2-tensor and alg:J3-tensor (S = A - tr(A)/3 I,
+//           tr(S S)/2, det S by LU with partial pivoting and reciprocal
+//           pivots, the LAPACK factorisation behind NumPy's determinant)
+//   both:   Delta = 4 J2^3 - 27 J3^2.
+
+__device__ __forceinline__ Inv invariants_general_naive(const Gen &A)
+{
+    const double A00 = A.a00, A01 = A.a01, A02 = A.a02, A10 = A.a10, A11 = A.a11, A12 = A.a12, A20 = A.a20,
+                 A21 = A.a21, A22 = A.a22;
+    Inv r;
+    r.i1 = (A00 + A11) + A22;
+    r.j2 = (A00 * A00 - A00 * A11 - A00 * A22 + 3 * A01 * A10 + 3 * A02 * A20 + A11 * A11 - A11 * A22 +
+            3 * A12 * A21 + A22 * A22) / 3.0;
+    r.j3 = (2 * A00 * A00 * A00 - 3 * A00 * A00 * A11 - 3 * A00 * A00 * A22 + 9 * A00 * A01 * A10 +
+            9 * A00 * A02 * A20 - 3 * A00 * A11 * A11 + 12 * A00 * A11 * A22 - 18 * A00 * A12 * A21 -
+            3 * A00 * A22 * A22 + 9 * A01 * A10 * A11 - 18 * A01 * A10 * A22 + 27 * A01 * A12 * A20 +
+            27 * A02 * A10 * A21 - 18 * A02 * A11 * A20 + 9 * A02 * A20 * A22 + 2 * A11 * A11 * A11 -
+            3 * A11 * A11 * A22 + 9 * A11 * A12 * A21 - 3 * A11 * A22 * A22 + 9 * A12 * A21 * A22 +
+            2 * A22 * A22 * A22) / 27.0;
+    r.disc = 4.0 * r.j2 * r.j2 * r.j2 - 27.0 * r.j3 * r.j3;
+    return r;
+}
+
+// one elimination step of LU with partial pivoting on column c of the 3x3
+// row-major m (rows c..2), as selects: the first row with the largest
+// magnitude is the pivot, rows are swapped (sign flipped), and rows below are
+// updated with l = m[r][c] * (1 / pivot) unless the pivot is zero.
+template <int C> __device__ __forceinline__ void lu_step(double m[9], double &sign)
+{
+    int p = C;
+#pragma unroll
+    for (int r = C + 1; r < 3; ++r)
+        p = fabs(m[3 * r + C]) > fabs(m[3 * p + C]) ? r : p;
+#pragma unroll
+    for (int r = C + 1; r < 3; ++r) {
+        const bool sw = p == r;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double a = m[3 * C + k], b = m[3 * r + k];
+            m[3 * C + k] = sw ? b : a;
+            m[3 * r + k] = sw ? a : b;
+        }
+        sign = sw ? -sign : sign;
+    }
+    const double piv = m[3 * C + C];
+    const bool live = piv != 0.0;
+    const double inv = 1.0 / piv;
+#pragma unroll
+    for (int r = C + 1; r < 3; ++r) {
+        const double l = m[3 * r + C] * inv;
+#pragma unroll
+        for (int k = C + 1; k < 3; ++k) {
+            const double upd = m[3 * r + k] - l * m[3 * C + k];
+            m[3 * r + k] = live ? upd : m[3 * r + k];
+        }
+    }
+}
+
+__device__ __forceinline__ Inv invariants_general_tensor(const Gen &A)
+{
+    Inv r;
+    r.i1 = (A.a00 + A.a11) + A.a22;
+    const double mean = r.i1 / 3.0;
+    double S[9] = {A.a00 - mean, A.a01, A.a02, A.a10, A.a11 - mean, A.a12, A.a20, A.a21, A.a22 - mean};
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double sii = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            sii = sii + S[3 * i + k] * S[3 * k + i];
+        tr = tr + sii;
+    }
+    r.j2 = tr / 2.0;
+    double sign = 1.0;
+    lu_step<0>(S, sign);
+    lu_step<1>(S, sign);
+    r.j3 = sign * (S[0] * S[4] * S[8]);
+    r.disc = 4.0 * r.j2 * r.j2 * r.j2 - 27.0 * r.j3 * r.j3;
+    return r;
+}
+
 // ================================================================ binary32
 // Two evaluations of binary32 batches.
 //
