@@ -37,6 +37,7 @@ BYTES = {
     "fwd_symmetric_f32": 6 * 4 + 3 * 4,
     "fwd_general_f32": 9 * 4 + 3 * 4,
     "bwd_general_f64": 9 * 8 + 3 * 8 + 9 * 8,
+    "mohr_coulomb_symmetric_f64": 6 * 8 + 8 + 6 * 8,
 }
 
 
@@ -317,6 +318,12 @@ def main():
             variant(f"config3 fwd symmetric f64 {acc_v}", "fwd_symmetric_f64", N_SYM,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(s64, "symmetric", acc_v, "soa", out=l3), "f64")
         del l3
+        # the paper's application: Mohr-Coulomb f and df/dsigma (S_yc = 100, m = 10)
+        f_mc = torch.empty(N_SYM, dtype=torch.float64, device=dev)
+        g_mc = [torch.empty(N_SYM, dtype=torch.float64, device=dev) for _ in range(6)]
+        variant("config3 mohr-coulomb f + df/dsigma symmetric f64 fma", "mohr_coulomb_symmetric_f64", N_SYM,
+                lambda: eig3.eig3_mohr_coulomb(s64, 100.0, 10.0, "symmetric", "fma", True, out=(f_mc, g_mc)), "f64")
+        del f_mc, g_mc
         s32 = [t.float() for t in s64]
         del s64
         torch.cuda.empty_cache()

@@ -152,6 +152,24 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
 int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *const g[3],
                           void *const grad_a[9], hipStream_t stream);
 
+/*
+ * Mohr-Coulomb yield function of stress tensors (Sec. "Application:
+ * Evaluation of the Mohr-Coulomb yield function in mechanics"):
+ *   f(sigma) = (1/S_yc) ((m + 1)/2) max_{i<j} (|s_i - s_j| + K (s_i + s_j)) - 1,
+ *   K = (m - 1)/(m + 1), m = S_yc / S_yt, s_i the principal stresses
+ * (eigenvalues of sigma from the same path as eig3_eigvals, per
+ * sigma->accuracy, including the comparator modes).
+ * f: n values, element type of sigma.
+ * dfds: NULL, or df/dsigma in the structure, layout and entry order of sigma.
+ *   GENERAL: the 9 entries of the full-matrix gradient.  SYMMETRIC: the 6
+ *   components of the (symmetric) tensor derivative; the derivative with
+ *   respect to a stored off-diagonal entry is twice its component.
+ *   +-Inf/NaN at the corners of the yield surface (s_1 = s_2 or s_2 = s_3).
+ * s_yc > 0 and m > 0 (finite), else EIG3_EINVAL.  Arithmetic in binary64.
+ */
+int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f, void *const dfds[9],
+                      hipStream_t stream);
+
 /* Static, human-readable name of a status code. */
 const char *eig3_status_string(int status);
 

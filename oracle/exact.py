@@ -280,6 +280,38 @@ def bound_scales(a9: Sequence[float]) -> dict[str, float]:
         }
 
 
+# ----------------------------------------------------------------------------
+# application: Mohr-Coulomb yield function
+# ----------------------------------------------------------------------------
+
+def mohr_coulomb(a9: Sequence[float], s_yc: float, m: float, dps: int = 80):
+    """f(sigma) = (1/S_yc) ((m+1)/2) max_{i<j} (|s_i - s_j| + K (s_i + s_j)) - 1,
+    K = (m-1)/(m+1), with the exact principal stresses s_i (Sec. "Application:
+    Evaluation of the Mohr-Coulomb yield function in mechanics", Eq.
+    mohr-coulomb-yield), and df/dsigma (9 row-major floats, full-matrix
+    gradient) through the maximizing pair: d|s_i - s_j| = sign(s_i - s_j)
+    (ds_i - ds_j), ds_k = E_k^T : dsigma.  Returns (f, grad)."""
+    lam = eigvals(a9, dps)
+    if any(isinstance(x, mpmath.mpc) for x in lam):
+        raise ValueError("complex spectrum")
+    with mpmath.workdps(dps):
+        mm = mpmath.mpf(m)
+        K = (mm - 1) / (mm + 1)
+        c = (mm + 1) / (2 * mpmath.mpf(s_yc))
+        best, bi, bj = None, 0, 0
+        for i in range(3):
+            for j in range(i + 1, 3):
+                v = abs(lam[i] - lam[j]) + K * (lam[i] + lam[j])
+                if best is None or v > best:
+                    best, bi, bj = v, i, j
+        f = c * best - 1
+        sgn = 1 if lam[bi] >= lam[bj] else -1
+        g = [0.0, 0.0, 0.0]
+        g[bi] = float(c * (sgn + K))
+        g[bj] = float(c * (-sgn + K))
+    return float(f), eigvals_vjp(a9, g, dps)
+
+
 def to_float(q: Fraction) -> float:
     """Correctly rounded binary64 value of an exact rational."""
     return float(q)

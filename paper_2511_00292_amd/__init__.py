@@ -24,7 +24,7 @@ from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EI
                     EIG3_NAIVE_TENSOR, EIG3_SOA, EIG3_SYMMETRIC, Eig3Error)
 
 __all__ = [
-    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eigvals", "Eig3Eigvals",
+    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eigvals", "Eig3Eigvals",
     "ENTRIES", "Eig3Error", "version",
 ]
 
@@ -157,6 +157,34 @@ def eig3_eigvals_backward(a: Batch, g: Batch, structure: str = "general", accura
         ptrs = [t.data_ptr() if n else 0 for t in res] + [0] * (9 - k)
     _capi.call_eigvals_backward(m, g_layout, gp, ptrs, _stream(dev))
     return res if layout == EIG3_AOS else tuple(res)
+
+
+def eig3_mohr_coulomb(sigma: Batch, s_yc: float, m: float, structure: str = "symmetric", accuracy: str = "fma",
+                      grad: bool = True, out=None):
+    """Mohr-Coulomb yield function f (n values) and, if ``grad``, df/dsigma
+    in the structure and layout of ``sigma`` (symmetric: the 6 components of
+    the tensor derivative).  Returns (f, dfds) with dfds None if not asked."""
+    mdesc, n, dtype, dev, layout, _keep = _matrices(sigma, structure, accuracy)
+    k = 9 if structure == "general" else 6
+    f, dfds = (out if out is not None else (None, None))
+    f = f if f is not None else torch.empty(n, dtype=dtype, device=dev)
+    _check_device_tensor(f, "f")
+    ptrs = None
+    if grad:
+        if layout == EIG3_AOS:
+            dfds = dfds if dfds is not None else torch.empty_like(sigma)
+            _check_device_tensor(dfds, "dfds")
+            ptrs = [dfds.data_ptr() if n else 0] + [0] * 8
+        else:
+            dfds = list(dfds) if dfds is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(k)]
+            for t in dfds:
+                _check_device_tensor(t, "dfds")
+            ptrs = [t.data_ptr() if n else 0 for t in dfds] + [0] * (9 - k)
+            dfds = tuple(dfds)
+    else:
+        dfds = None
+    _capi.call_mohr_coulomb(mdesc, s_yc, m, f.data_ptr() if n else 0, ptrs, _stream(dev))
+    return f, dfds
 
 
 class Eig3Eigvals(torch.autograd.Function):

@@ -61,6 +61,8 @@ def lib():
         l.eig3_eigvals.restype = ctypes.c_int
         l.eig3_eigvals_backward.argtypes = [pm, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         l.eig3_eigvals_backward.restype = ctypes.c_int
+        l.eig3_mohr_coulomb.argtypes = [pm, ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(vp), vp]
+        l.eig3_mohr_coulomb.restype = ctypes.c_int
         l.eig3_status_string.argtypes = [ctypes.c_int]
         l.eig3_status_string.restype = ctypes.c_char_p
         l.eig3_version.argtypes = []
@@ -102,3 +104,11 @@ def call_eigvals_backward(m: Eig3Matrices, g_layout: int, g, grads, stream: int)
     st = lib().eig3_eigvals_backward(ctypes.byref(m), g_layout, garr, oarr, ctypes.c_void_p(stream))
     if st != EIG3_OK:
         raise Eig3Error(st, "eig3_eigvals_backward")
+
+
+def call_mohr_coulomb(m: Eig3Matrices, s_yc: float, mm: float, f: int, grads, stream: int) -> None:
+    arr = (ctypes.c_void_p * 9)(*grads) if grads is not None else None
+    st = lib().eig3_mohr_coulomb(ctypes.byref(m), float(s_yc), float(mm), ctypes.c_void_p(f), arr,
+                                 ctypes.c_void_p(stream))
+    if st != EIG3_OK:
+        raise Eig3Error(st, "eig3_mohr_coulomb")

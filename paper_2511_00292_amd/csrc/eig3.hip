@@ -387,6 +387,59 @@ EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, Out9<T> out)
     });
 }
 
+// Mohr-Coulomb yield function f and, if Grad, df/dsigma (binary64
+// arithmetic for either storage type).  For symmetric storage df/dsigma is
+// the tensor derivative: its 6 components (the off-diagonal value is that of
+// each of the two symmetric positions).
+template <class T, int S, int L, int Acc, bool Grad>
+EIG3_KERNEL void k_mohr_coulomb(int64_t n, In9<T> in, double cf, double K, T *__restrict__ f, Out9<T> out)
+{
+    for_each_matrix<T, S, L>(n, in, [&](int64_t i, const Mat<T, S> &mt) {
+        constexpr int KS = Mat<T, S>::K;
+        Mat<double, S> m;
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            m.a[k] = double(mt.a[k]);
+        const Inv v = invariants_of<S, Acc>(m);
+        // the gradient kernel carries many pointers: its coefficients are
+        // immediates rather than SGPR-resident constants
+        const MohrCoulomb mc = mohr_coulomb<!Grad>(v, cf, K);
+        st(T(mc.f), f + i);
+        if constexpr (Grad) {
+            const Coef c = backward_coefficients(mc.t, mc.g1, 0.0, mc.g3);
+            double gr[9];
+            if constexpr (S == EIG3_GENERAL) {
+                backward_general(to_gen(m), c, gr);
+            } else {
+                const Sym y = to_sym(m);
+                backward_general(Gen{y.s00, y.s01, y.s02, y.s01, y.s11, y.s12, y.s02, y.s12, y.s22}, c, gr);
+            }
+            double o[KS];
+            if constexpr (S == EIG3_GENERAL) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    o[k] = gr[k];
+            } else {
+                o[0] = gr[0];
+                o[1] = gr[4];
+                o[2] = gr[8];
+                o[3] = 0.5 * (gr[1] + gr[3]);
+                o[4] = 0.5 * (gr[2] + gr[6]);
+                o[5] = 0.5 * (gr[5] + gr[7]);
+            }
+            if constexpr (L == EIG3_SOA) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    st(T(o[k]), out.p[k] + i);
+            } else {
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    st(T(o[k]), out.p[0] + KS * i + k);
+            }
+        }
+    });
+}
+
 // ------------------------------------------------------------------- host
 int device_cus()
 {
@@ -689,6 +742,65 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
         });
     };
     if (A->dtype == EIG3_F32)
+        launch(float{});
+    else
+        launch(double{});
+    return launched();
+}
+
+int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f, void *const dfds[9],
+                      hipStream_t stream)
+{
+    int st = check_matrices(sigma);
+    if (st != EIG3_OK)
+        return st;
+    if (!(s_yc > 0.0) || !(m > 0.0) || s_yc > 1e300 || m > 1e300)
+        return EIG3_EINVAL;
+    if (sigma->n == 0)
+        return EIG3_OK;
+    if (f == nullptr)
+        return EIG3_EINVAL;
+    const int K = sigma->structure == EIG3_GENERAL ? 9 : 6;
+    const bool grad = dfds != nullptr;
+    const int nout = grad ? (sigma->layout == EIG3_SOA ? K : 1) : 0;
+    void *outs[10];
+    outs[0] = f;
+    for (int k = 0; k < nout; ++k)
+        outs[1 + k] = dfds[k];
+    // f holds n values; every gradient array n (SoA) or n*K (AoS) values
+    if ((st = check_outputs(sigma, outs, 1, size_t(sigma->n))) != EIG3_OK)
+        return st;
+    if (grad) {
+        if ((st = check_outputs(sigma, outs + 1, nout, size_t(sigma->n) * (nout == 1 ? K : 1))) != EIG3_OK)
+            return st;
+        const size_t es = elem_size(sigma->dtype);
+        const Range fr{uintptr_t(f), uintptr_t(f) + size_t(sigma->n) * es};
+        for (int k = 0; k < nout; ++k) {
+            const Range o{uintptr_t(outs[1 + k]), uintptr_t(outs[1 + k]) + size_t(sigma->n) * (nout == 1 ? K : 1) * es};
+            if (overlaps(o, fr))
+                return EIG3_EINVAL;
+        }
+    }
+    const double cf = (m + 1.0) / (2.0 * s_yc);
+    const double Kc = (m - 1.0) / (m + 1.0);
+    const dim3 grid(unsigned(grid_for(sigma->n, sigma->layout))), block(kBlock);
+    auto launch = [&](auto tag) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(sigma);
+        Out9<T> out;
+        for (int k = 0; k < 9; ++k)
+            out.p[k] = k < nout ? static_cast<T *>(outs[1 + k]) : nullptr;
+        T *fo = static_cast<T *>(f);
+        dispatch_sla4(sigma->structure, sigma->layout, sigma->accuracy, [&](auto S, auto L, auto Acc) {
+            if (grad)
+                hipLaunchKernelGGL((k_mohr_coulomb<T, S.value, L.value, Acc.value, true>), grid, block, 0, stream,
+                                   sigma->n, in, cf, Kc, fo, out);
+            else
+                hipLaunchKernelGGL((k_mohr_coulomb<T, S.value, L.value, Acc.value, false>), grid, block, 0,
+                                   stream, sigma->n, in, cf, Kc, fo, out);
+        });
+    };
+    if (sigma->dtype == EIG3_F32)
         launch(float{});
     else
         launch(double{});

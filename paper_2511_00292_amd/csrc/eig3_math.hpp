@@ -801,9 +801,8 @@ struct Coef {
     double a, b;
 };
 
-__device__ __forceinline__ Coef backward_coefficients(const Inv &v, double g1, double g2, double g3)
+__device__ __forceinline__ Coef backward_coefficients(const Trig &t, double g1, double g2, double g3)
 {
-    const Trig t = trig_from_invariants<false>(v);
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
     // gaps of the |J3| configuration; for J3 < 0 they swap roles
@@ -815,12 +814,20 @@ __device__ __forceinline__ Coef backward_coefficients(const Inv &v, double g1, d
     const double G1 = e12 * e13;   // (mu1 - mu2)(mu1 - mu3)
     const double G2 = -e12 * e23;  // (mu2 - mu1)(mu2 - mu3)
     const double G3 = e13 * e23;   // (mu3 - mu1)(mu3 - mu2)
-    const double q1 = g1 / G1, q2 = g2 / G2, q3 = g3 / G3;
+    // a zero weight contributes nothing, also where its gap product vanishes
+    const double q1 = g1 == 0.0 ? 0.0 : g1 / G1;
+    const double q2 = g2 == 0.0 ? 0.0 : g2 / G2;
+    const double q3 = g3 == 0.0 ? 0.0 : g3 / G3;
     Coef c;
     c.gsum3 = (g1 + g2 + g3) * kThird;
     c.b = q1 + q2 + q3;
     c.a = fma_(q1, m1, fma_(q2, m2, q3 * m3));
     return c;
+}
+
+__device__ __forceinline__ Coef backward_coefficients(const Inv &v, double g1, double g2, double g3)
+{
+    return backward_coefficients(trig_from_invariants<false>(v), g1, g2, g3);
 }
 
 // grad (row-major 9) for a general matrix
@@ -853,6 +860,39 @@ __device__ __forceinline__ void backward_general(const Gen &A, const Coef &k, do
     grad[6] = fma_(k.a, s02, k.b * c20);
     grad[7] = fma_(k.a, s12, k.b * c21);
     grad[8] = fma_(k.a, s22, fma_(k.b, c22, k.gsum3));
+}
+
+// ============================================================ Mohr-Coulomb
+// Yield function of the paper's application section:
+//   f(sigma) = (1/S_yc) ((m + 1)/2) max_{i<j} (|s_i - s_j| + K (s_i + s_j)) - 1,
+//   K = (m - 1)/(m + 1), s_1 <= s_2 <= s_3 the principal stresses.
+// With ascending s, |s_i - s_j| = s_j - s_i for i < j, and for |K| < 1 the
+// pair (1, 3) attains the maximum, so df/dsigma = cf ((1 + K) E_3 - (1 - K) E_1)
+// with cf = (m + 1)/(2 S_yc) and E_k = d(s_k)/dsigma: the adjoint with
+// g = (cf (K - 1), 0, cf (1 + K)).  At s_1 = s_2 or s_2 = s_3 (the corners of
+// the yield surface) f is not differentiable and the gradient is +-Inf/NaN.
+struct MohrCoulomb {
+    double f;
+    double g1, g3; // weights of d(s_1)/dsigma and d(s_3)/dsigma
+    Trig t;        // the triple-angle quantities, reused by the gradient
+};
+
+template <bool Table = true> __device__ __forceinline__ MohrCoulomb mohr_coulomb(const Inv &v, double cf, double K)
+{
+    const Trig t = trig_from_invariants<Table>(v);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    const double s1 = t.mean + m1, s2 = t.mean + m2, s3 = t.mean + m3;
+    const double p12 = (s2 - s1) + K * (s1 + s2);
+    const double p13 = (s3 - s1) + K * (s1 + s3);
+    const double p23 = (s3 - s2) + K * (s2 + s3);
+    const double pm = fmax(fmax(p12, p13), p23);
+    MohrCoulomb r;
+    r.f = fma_(cf, pm, -1.0);
+    r.g1 = cf * (K - 1.0);
+    r.g3 = cf * (1.0 + K);
+    r.t = t;
+    return r;
 }
 
 } // namespace eig3

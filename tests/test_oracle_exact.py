@@ -242,3 +242,25 @@ def test_exhaustive_small_integer_triangular():
         lo = [d[0], 0, 0, 5, d[1], 0, -4, 1, d[2]]
         dg = [d[0], 0, 0, 0, d[1], 0, 0, 0, d[2]]
         assert exact.invariants(up) == exact.invariants(dg) == exact.invariants(lo)
+
+
+def test_mohr_coulomb_closed_form_and_fd():
+    """For |K| < 1 the pair (1, 3) attains the maximum, so
+    f = (m s_3 - s_1)/S_yc - 1 and df/dsigma = (m E_3 - E_1)/S_yc; checked
+    against that closed form and central differences of the exact f."""
+    rng = np.random.default_rng(18)
+    for _ in range(12):
+        s = rng.standard_normal(6) * 50
+        a = [s[0], s[3], s[4], s[3], s[1], s[5], s[4], s[5], s[2]]
+        m, syc = float(rng.uniform(1.5, 12)), float(rng.uniform(20, 200))
+        f, g = exact.mohr_coulomb(a, syc, m)
+        lam = [float(x) for x in exact.eigvals(a)]
+        assert f == pytest.approx((m * lam[2] - lam[0]) / syc - 1, rel=1e-14, abs=1e-14)
+        ref = exact.eigvals_vjp(a, [-1 / syc, 0.0, m / syc])
+        np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-15)
+        h = 1e-6
+        for e in (0, 1, 4, 8):
+            ap = list(a); ap[e] += h
+            am = list(a); am[e] -= h
+            fd = (exact.mohr_coulomb(ap, syc, m, 40)[0] - exact.mohr_coulomb(am, syc, m, 40)[0]) / (2 * h)
+            assert abs(fd - g[e]) < 1e-6
