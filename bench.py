@@ -38,6 +38,7 @@ BYTES = {
     "fwd_general_f32": 9 * 4 + 3 * 4,
     "bwd_general_f64": 9 * 8 + 3 * 8 + 9 * 8,
     "mohr_coulomb_symmetric_f64": 6 * 8 + 8 + 6 * 8,
+    "eigenprojectors_general_f64": 9 * 8 + 27 * 8,
 }
 
 
@@ -289,6 +290,11 @@ def main():
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a, "general", acc_v, "soa", out=lam), "f64")
             variant(f"config5 bwd general f64 {acc_v}", "bwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals_backward(a, g, "general", acc_v, out=grad), "f64")
+        # eigenprojectors E_1..E_3 (27 outputs per matrix, write-heavy)
+        eproj = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(27)]
+        variant("config5 eigenprojectors general f64 fma", "eigenprojectors_general_f64", N_MAIN,
+                lambda: eig3.eig3_eigenprojectors(a, "general", "fma", "soa", out=eproj), "f64")
+        del eproj
         # the same batch as one (n, 3, 3) array of structures (LDS-staged loads)
         a_aos = torch.stack(a, dim=1).contiguous()
         lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)

@@ -170,6 +170,23 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
 int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f, void *const dfds[9],
                       hipStream_t stream);
 
+/*
+ * Eigenprojectors E_k = prod_{j != k} (A - lambda_j I) / (lambda_k - lambda_j),
+ * k = 1, 2, 3 for the ascending eigenvalues: the projectors behind the
+ * relation E_k^T = d(lambda_k)/dA that the paper uses for closed-form
+ * functions of matrices (Sec. "Introduction and motivation"), evaluated
+ * through the invariants as E_k = I/3 + (mu_k S + dev(cof S)^T) / G_k,
+ * S = dev A, G_k = (lambda_k - lambda_i)(lambda_k - lambda_j).
+ * GENERAL: 9 row-major entries per projector; SYMMETRIC: the 6 components
+ * (A00 A11 A22 A01 A02 A12 order) of each symmetric projector.
+ * out_layout EIG3_SOA: E[K*k + e] -> n values of entry e of E_(k+1)
+ *   (K = 9 or 6; 27 or 18 pointers).  EIG3_AOS: E[0] -> n*3*K values,
+ *   per matrix E_1, E_2, E_3 one after the other.
+ * Undefined at repeated eigenvalues (+-Inf/NaN).  Arithmetic in binary64,
+ * results in the element type of A.
+ */
+int eig3_eigenprojectors(const eig3_matrices *A, int32_t out_layout, void *const E[27], hipStream_t stream);
+
 /* Static, human-readable name of a status code. */
 const char *eig3_status_string(int status);
 

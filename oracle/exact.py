@@ -246,6 +246,26 @@ def eigvals_vjp(a9: Sequence[float], g: Sequence[float], dps: int = 80) -> list[
         return [float(grad[r][c]) for r in range(3) for c in range(3)]
 
 
+def eigenprojectors(a9: Sequence[float], dps: int = 80) -> list[float]:
+    """E_1, E_2, E_3 (ascending eigenvalues), 27 floats, each row-major:
+    the Frobenius covariants E_k = prod_{j != k} (A - lambda_j I) /
+    (lambda_k - lambda_j) of a real, distinct spectrum (the projectors of the
+    relation E_k^T = d(lambda_k)/dA in Sec. "Introduction and motivation")."""
+    lam = eigvals(a9, dps)
+    if any(isinstance(x, mpmath.mpc) for x in lam):
+        raise ValueError("complex spectrum")
+    with mpmath.workdps(dps):
+        a = [[mpmath.mpf(float(a9[3 * i + j])) for j in range(3)] for i in range(3)]
+        out = []
+        for k in range(3):
+            i, j = [m for m in range(3) if m != k]
+            p = [[a[r][c] - (lam[i] if r == c else 0) for c in range(3)] for r in range(3)]
+            q = [[a[r][c] - (lam[j] if r == c else 0) for c in range(3)] for r in range(3)]
+            den = (lam[k] - lam[i]) * (lam[k] - lam[j])
+            out += [float(sum(p[r][t] * q[t][c] for t in range(3)) / den) for r in range(3) for c in range(3)]
+        return out
+
+
 # ----------------------------------------------------------------------------
 # stability-bound scales (C = 1, Frobenius norms, lowest-order term)
 # ----------------------------------------------------------------------------

@@ -24,7 +24,8 @@ from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EI
                     EIG3_NAIVE_TENSOR, EIG3_SOA, EIG3_SYMMETRIC, Eig3Error)
 
 __all__ = [
-    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eigvals", "Eig3Eigvals",
+    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors", "eigvals",
+    "Eig3Eigvals",
     "ENTRIES", "Eig3Error", "version",
 ]
 
@@ -185,6 +186,28 @@ def eig3_mohr_coulomb(sigma: Batch, s_yc: float, m: float, structure: str = "sym
         dfds = None
     _capi.call_mohr_coulomb(mdesc, s_yc, m, f.data_ptr() if n else 0, ptrs, _stream(dev))
     return f, dfds
+
+
+def eig3_eigenprojectors(a: Batch, structure: str = "general", accuracy: str = "fma", out_layout: str = "aos",
+                         out=None):
+    """Eigenprojectors E_1, E_2, E_3 of each matrix (ascending eigenvalues).
+    out_layout 'aos': an (n, 3, K) tensor (K = 9 row-major entries, or the 6
+    symmetric components); 'soa': a tuple of 3K n-vectors, slot K*k + e."""
+    m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
+    k = 9 if structure == "general" else 6
+    if out_layout == "aos":
+        res = out if out is not None else torch.empty((n, 3, k), dtype=dtype, device=dev)
+        _check_device_tensor(res, "out")
+        _capi.call_eigenprojectors(m, EIG3_AOS, [res.data_ptr() if n else 0] + [0] * 26, _stream(dev))
+        return res
+    if out_layout == "soa":
+        res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(3 * k)]
+        for t in res:
+            _check_device_tensor(t, "out")
+        _capi.call_eigenprojectors(m, EIG3_SOA, [t.data_ptr() if n else 0 for t in res] + [0] * (27 - 3 * k),
+                                   _stream(dev))
+        return tuple(res)
+    raise ValueError("out_layout must be 'aos' or 'soa'")
 
 
 class Eig3Eigvals(torch.autograd.Function):

@@ -77,6 +77,9 @@ template <class T> struct Out4 {
 template <class T> struct Out3 {
     T *p[3];
 };
+template <class T> struct Out27 {
+    T *p[27];
+};
 template <class T> struct G3 {
     const T *p[3];
 };
@@ -436,6 +439,60 @@ EIG3_KERNEL void k_mohr_coulomb(int64_t n, In9<T> in, double cf, double K, T *__
                 for (int k = 0; k < KS; ++k)
                     st(T(o[k]), out.p[0] + KS * i + k);
             }
+        }
+    });
+}
+
+// Eigenprojectors E_1, E_2, E_3 (ascending eigenvalues); binary64
+// arithmetic for either storage type.  GENERAL: 9 entries per projector;
+// SYMMETRIC: the 6 stored components of each (symmetric) projector.  Output
+// slot 9k+e (general) or 6k+e (symmetric): SoA pointer per slot, or AoS with
+// 27 (18) values per matrix.
+template <class T, int S, int L, int OL, int Acc>
+EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, Out27<T> out)
+{
+    for_each_matrix<T, S, L>(n, in, [&](int64_t i, const Mat<T, S> &mt) {
+        constexpr int KS = Mat<T, S>::K;
+        Mat<double, S> m;
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            m.a[k] = double(mt.a[k]);
+        const Inv v = invariants_of<S, Acc>(m);
+        const Trig t = trig_from_invariants<false>(v);
+        Gen a;
+        if constexpr (S == EIG3_GENERAL) {
+            a = to_gen(m);
+        } else {
+            const Sym y = to_sym(m);
+            a = Gen{y.s00, y.s01, y.s02, y.s01, y.s11, y.s12, y.s02, y.s12, y.s22};
+        }
+        double E[27];
+        eigenprojectors_general(a, t, E);
+        constexpr int NO = 3 * KS;
+        double o[NO];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if constexpr (S == EIG3_GENERAL) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e)
+                    o[9 * k + e] = E[9 * k + e];
+            } else {
+                o[6 * k + 0] = E[9 * k + 0];
+                o[6 * k + 1] = E[9 * k + 4];
+                o[6 * k + 2] = E[9 * k + 8];
+                o[6 * k + 3] = 0.5 * (E[9 * k + 1] + E[9 * k + 3]);
+                o[6 * k + 4] = 0.5 * (E[9 * k + 2] + E[9 * k + 6]);
+                o[6 * k + 5] = 0.5 * (E[9 * k + 5] + E[9 * k + 7]);
+            }
+        }
+        if constexpr (OL == EIG3_SOA) {
+#pragma unroll
+            for (int e = 0; e < NO; ++e)
+                st(T(o[e]), out.p[e] + i);
+        } else {
+#pragma unroll
+            for (int e = 0; e < NO; ++e)
+                st(T(o[e]), out.p[0] + NO * i + e);
         }
     });
 }
@@ -801,6 +858,45 @@ int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f
         });
     };
     if (sigma->dtype == EIG3_F32)
+        launch(float{});
+    else
+        launch(double{});
+    return launched();
+}
+
+int eig3_eigenprojectors(const eig3_matrices *A, int32_t out_layout, void *const E[27], hipStream_t stream)
+{
+    int st = check_matrices(A);
+    if (st != EIG3_OK)
+        return st;
+    if (E == nullptr || !valid_enum(out_layout, 1))
+        return EIG3_EINVAL;
+    if (A->n == 0)
+        return EIG3_OK;
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    const int nout = out_layout == EIG3_SOA ? 3 * K : 1;
+    void *outs[27];
+    for (int k = 0; k < nout; ++k)
+        outs[k] = E[k];
+    if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? 3 * K : 1))) != EIG3_OK)
+        return st;
+    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
+    auto launch = [&](auto tag) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(A);
+        Out27<T> out;
+        for (int k = 0; k < 27; ++k)
+            out.p[k] = k < nout ? static_cast<T *>(outs[k]) : nullptr;
+        dispatch_sla4(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            if (out_layout == EIG3_AOS)
+                hipLaunchKernelGGL((k_eigenprojectors<T, S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0,
+                                   stream, A->n, in, out);
+            else
+                hipLaunchKernelGGL((k_eigenprojectors<T, S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0,
+                                   stream, A->n, in, out);
+        });
+    };
+    if (A->dtype == EIG3_F32)
         launch(float{});
     else
         launch(double{});

@@ -895,4 +895,44 @@ template <bool Table = true> __device__ __forceinline__ MohrCoulomb mohr_coulomb
     return r;
 }
 
+// ============================================================ eigenprojectors
+// E_k = prod_{j != k} (A - lambda_j I) / (lambda_k - lambda_j), the projector
+// onto the k-th eigenspace; the paper relates it to the eigenvalue
+// derivative, E_k^T = d(lambda_k)/dA (Sec. "Introduction and motivation").
+// Through the invariants (as for the adjoint), with S = dev A:
+//   E_k^T = I/3 + (mu_k S^T + dev(cof S)) / G_k,  G_k = prod_{j != k}(mu_k - mu_j),
+// so E_k = I/3 + (mu_k S + dev(cof S)^T) / G_k.  Row-major 9 entries per k.
+__device__ __forceinline__ void eigenprojectors_general(const Gen &A, const Trig &t, double E[27])
+{
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    const double e13 = t.r * fma_(3.0, t.c, kSqrt3 * t.s);
+    const double e23p = t.r * fma_(3.0, t.c, -kSqrt3 * t.s);
+    const double e12p = 2.0 * kSqrt3 * t.r * t.s;
+    const double e12 = t.neg ? e23p : e12p;
+    const double e23 = t.neg ? e12p : e23p;
+    const double inv[3] = {1.0 / (e12 * e13), -1.0 / (e12 * e23), 1.0 / (e13 * e23)};
+    const double mu[3] = {m1, m2, m3};
+    const Diag g = diag_part(A.a00, A.a11, A.a22);
+    const double S[9] = {(g.d0 + g.d1) * kThird, A.a01, A.a02, A.a10, (g.d2 - g.d0) * kThird, A.a12,
+                         A.a20, A.a21, -(g.d1 + g.d2) * kThird};
+    // cofactor matrix of S, made deviatoric
+    double C[9] = {fma_(S[4], S[8], -S[5] * S[7]), fma_(S[5], S[6], -S[3] * S[8]), fma_(S[3], S[7], -S[4] * S[6]),
+                   fma_(S[2], S[7], -S[1] * S[8]), fma_(S[0], S[8], -S[2] * S[6]), fma_(S[1], S[6], -S[0] * S[7]),
+                   fma_(S[1], S[5], -S[2] * S[4]), fma_(S[2], S[3], -S[0] * S[5]), fma_(S[0], S[4], -S[1] * S[3])};
+    const double tr3 = ((C[0] + C[4]) + C[8]) * kThird;
+    C[0] -= tr3;
+    C[4] -= tr3;
+    C[8] -= tr3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double a = mu[k] * inv[k], b = inv[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                E[9 * k + 3 * r + c] = fma_(a, S[3 * r + c], fma_(b, C[3 * c + r], r == c ? kThird : 0.0));
+    }
+}
+
 } // namespace eig3

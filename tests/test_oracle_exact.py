@@ -264,3 +264,24 @@ def test_mohr_coulomb_closed_form_and_fd():
             am = list(a); am[e] -= h
             fd = (exact.mohr_coulomb(ap, syc, m, 40)[0] - exact.mohr_coulomb(am, syc, m, 40)[0]) / (2 * h)
             assert abs(fd - g[e]) < 1e-6
+
+
+def test_eigenprojector_identities():
+    """sum E_k = I, sum lambda_k E_k = A, E_k E_j = delta_kj E_k, and
+    E_k = x_k y_k^T with x_k = V[:, k], y_k^T = V^-1[k, :] of the generator."""
+    import workloads as w
+    c = w.config5(6, seed=79, with_basis=True)
+    for m in range(6):
+        a = c["a"][m]
+        e = np.array(exact.eigenprojectors(a)).reshape(3, 3, 3)
+        lam = [float(x) for x in exact.eigvals(a)]
+        am = np.array(a).reshape(3, 3)
+        np.testing.assert_allclose(e.sum(0), np.eye(3), atol=1e-10)
+        np.testing.assert_allclose(sum(lam[k] * e[k] for k in range(3)), am, atol=1e-10)
+        for k in range(3):
+            for j in range(3):
+                np.testing.assert_allclose(e[k] @ e[j], e[k] if k == j else 0 * e[k], atol=1e-8)
+        v = c["v"][m].reshape(3, 3)
+        vi = c["vinv"][m].reshape(3, 3)
+        for k in range(3):
+            np.testing.assert_allclose(e[k], np.outer(v[:, k], vi[k, :]), atol=1e-9 * np.abs(e[k]).max())
