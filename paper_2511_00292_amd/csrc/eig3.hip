@@ -38,6 +38,11 @@ constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 #ifndef EIG3_PIPELINE
 #define EIG3_PIPELINE 0
 #endif
+//  EIG3_AOS_DIRECT    1: array-of-structures input is loaded lane by lane
+//                     instead of through the LDS tile
+#ifndef EIG3_AOS_DIRECT
+#define EIG3_AOS_DIRECT 0
+#endif
 #ifndef EIG3_BLOCKS_PER_CU
 #define EIG3_BLOCKS_PER_CU 4
 #endif
@@ -233,6 +238,17 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Bod
             body(i, m);
         }
 #endif
+    } else if constexpr (EIG3_AOS_DIRECT) {
+        // each lane loads its own K consecutive values; the cache lines of a
+        // wave's contiguous span are shared by its K load instructions
+        const int64_t stride = int64_t(gridDim.x) * kBlock;
+        for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+            Mat<T, S> m;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                m.a[k] = ld(in.p[0] + K * i + k);
+            body(i, m);
+        }
     } else {
         __shared__ AosTile<T, K> tile;
         const int64_t stride = int64_t(gridDim.x) * kBlock;
@@ -570,12 +586,16 @@ int check_matrices(const eig3_matrices *A)
     return EIG3_OK;
 }
 
+constexpr int kMaxOutputs = 27; // eig3_eigenprojectors, general SoA
+
 int check_outputs(const eig3_matrices *A, void *const *outs, int nout, size_t count_each)
 {
     Range in[9];
     const int nin = input_ranges(A, in);
     const size_t es = elem_size(A->dtype);
-    Range o[9];
+    Range o[kMaxOutputs];
+    if (nout < 0 || nout > kMaxOutputs)
+        return EIG3_EINVAL;
     for (int j = 0; j < nout; ++j) {
         if (outs[j] == nullptr || !aligned(outs[j], es))
             return EIG3_EINVAL;

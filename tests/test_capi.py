@@ -110,3 +110,22 @@ def test_python_binding_rejects_host_tensors():
         eig3.eig3_eigvals(torch.zeros(4, 9, dtype=torch.float64))
     with pytest.raises(ValueError):
         eig3.eig3_eigvals([torch.zeros(4, dtype=torch.float64)] * 3)
+
+
+def test_eigenprojector_outputs_all_checked(lib):
+    """27 structure-of-arrays outputs are each range-checked (regression: the
+    host check once held room for 9); the last one aliases an input, so the
+    call is rejected after every slot was examined."""
+    n = 1024
+    ins = [0x20000000 + j * n * 8 for j in range(9)]
+    m = _mat(n=n, ptrs=ins)
+    outs = [0x40000000 + j * 0x100000 for j in range(26)] + [ins[0]]
+    arr = (ctypes.c_void_p * 27)(*outs)
+    assert lib.eig3_eigenprojectors(ctypes.byref(m), 0, arr, None) == capi.EIG3_EINVAL
+    # Mohr-Coulomb: the gradient arrays and f are checked against each other
+    f = 0x50000000
+    grads = (ctypes.c_void_p * 9)(*([f] + [0x60000000 + j * 0x100000 for j in range(8)]))
+    assert lib.eig3_mohr_coulomb(ctypes.byref(m), ctypes.c_double(100.0), ctypes.c_double(10.0),
+                                 ctypes.c_void_p(f), grads, None) == capi.EIG3_EINVAL
+    assert lib.eig3_mohr_coulomb(ctypes.byref(m), ctypes.c_double(0.0), ctypes.c_double(10.0),
+                                 ctypes.c_void_p(f), None, None) == capi.EIG3_EINVAL
