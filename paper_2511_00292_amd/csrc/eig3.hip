@@ -73,17 +73,10 @@ template <class T> __device__ __forceinline__ void st(T v, T *p)
 template <class T> struct In9 {
     const T *p[9];
 };
-template <class T> struct Out9 {
-    T *p[9];
-};
-template <class T> struct Out4 {
-    T *p[4];
-};
-template <class T> struct Out3 {
-    T *p[3];
-};
-template <class T> struct Out27 {
-    T *p[27];
+// KO output slots per matrix: one array per slot (structure of arrays,
+// p[e] + i) or one array of KO values per matrix (array of structures, p[0])
+template <class T, int KO> struct OutK {
+    T *p[KO];
 };
 template <class T> struct G3 {
     const T *p[3];
@@ -92,12 +85,11 @@ template <class T> struct G3 {
 // ------------------------------------------------------------------ loads
 // AoS staging: the workgroup copies its contiguous span of kBlock matrices
 // (kBlock*K elements) into LDS with 16-byte loads, then each lane reads its K
-// entries.  K = 9 (general) or 6 (symmetric); the LDS row stride K+1 keeps the
-// per-lane reads on distinct banks for K = 9.
-template <class T, int K> struct alignas(16) AosTile {
-    static constexpr int kStride = (K % 2 == 1) ? K : K + 1;
-    T v[kBlock * kStride];
-};
+// entries.  K = 9 (general) or 6 (symmetric).  binary64 rows of even length
+// are padded by one value so that the per-lane 8-byte reads spread over the
+// banks; binary32 rows stay unpadded, which lets the staging loop store its
+// 16-byte vectors whole.
+template <class T, int K> constexpr int aos_stride() { return (sizeof(T) == 8 && K % 2 == 0) ? K + 1 : K; }
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -112,7 +104,7 @@ template <> struct Vec16<float> {
 };
 
 template <class T, int K>
-__device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t first, int64_t n, AosTile<T, K> &tile)
+__device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t first, int64_t n, T *tile)
 {
     // elements [first*K, min(n, first+kBlock)*K) of base; the span starts at
     // a multiple of kBlock*K elements, so its 16-byte alignment is that of
@@ -120,7 +112,7 @@ __device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t fi
     const int64_t m_end = (first + kBlock < n) ? first + kBlock : n;
     const int count = int((m_end - first) * K);
     const T *src = base + first * K;
-    constexpr int kS = AosTile<T, K>::kStride;
+    constexpr int kS = aos_stride<T, K>();
     int done = 0;
     if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
         using V = typename Vec16<T>::type;
@@ -131,12 +123,12 @@ __device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t fi
             const V x = ld(vsrc + v);
             if constexpr (kS == K) {
                 // unpadded rows: the tile is the span itself
-                reinterpret_cast<V *>(tile.v)[v] = x;
+                reinterpret_cast<V *>(tile)[v] = x;
             } else {
 #pragma unroll
                 for (int j = 0; j < NV; ++j) {
                     const int e = v * NV + j, m = e / K, k = e - m * K;
-                    tile.v[m * kS + k] = x[j];
+                    tile[m * kS + k] = x[j];
                 }
             }
         }
@@ -144,8 +136,32 @@ __device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t fi
     }
     for (int e = done + threadIdx.x; e < count; e += kBlock) {
         const int m = e / K, k = e - m * K;
-        tile.v[m * kS + k] = ld(src + e);
+        tile[m * kS + k] = ld(src + e);
     }
+}
+
+// The reverse for outputs: the workgroup's staged rows (KO values per matrix,
+// contiguous in LDS) are written to the contiguous output span with 16-byte
+// stores where the span is 16-byte aligned.
+template <class T, int KO>
+__device__ __forceinline__ void aos_flush(T *__restrict__ base, int64_t first, int64_t n, const T *tile)
+{
+    const int64_t m_end = (first + kBlock < n) ? first + kBlock : n;
+    const int count = int((m_end - first) * KO);
+    T *dst = base + first * KO;
+    int done = 0;
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        using V = typename Vec16<T>::type;
+        constexpr int NV = Vec16<T>::N;
+        const int nvec = count / NV;
+        V *vdst = reinterpret_cast<V *>(dst);
+        const V *vtile = reinterpret_cast<const V *>(tile);
+        for (int v = threadIdx.x; v < nvec; v += kBlock)
+            st(vtile[v], vdst + v);
+        done = nvec * NV;
+    }
+    for (int e = done + threadIdx.x; e < count; e += kBlock)
+        st(tile[e], dst + e);
 }
 
 template <class T, int S> struct Mat;
@@ -202,10 +218,26 @@ template <int S, int Acc> __device__ __forceinline__ Inv invariants_of(const Mat
     }
 }
 
-// Per-matrix driver shared by the three entry points: loads matrix i (from
-// SoA pointers or the LDS tile) and calls body(i, matrix).
-template <class T, int S, int L, class Body>
-__device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Body body)
+template <class T, int KO>
+__device__ __forceinline__ void store_rows(const OutK<T, KO> &out, int layout, int64_t i, const double (&o)[KO])
+{
+    if (layout == EIG3_SOA) {
+#pragma unroll
+        for (int e = 0; e < KO; ++e)
+            st(T(o[e]), out.p[e] + i);
+    } else {
+#pragma unroll
+        for (int e = 0; e < KO; ++e)
+            st(T(o[e]), out.p[0] + KO * i + e);
+    }
+}
+
+// Per-matrix driver shared by every kernel: loads matrix i (SoA pointers or
+// the LDS tile), calls body(i, matrix, o) which fills the KO output values
+// o[], and stores them in output layout OL.  For AoS input and AoS output the
+// rows go back through LDS and leave with 16-byte stores.
+template <class T, int S, int L, int KO, int OL, class Body>
+__device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, const OutK<T, KO> &out, Body body)
 {
     constexpr int K = Mat<T, S>::K;
     if constexpr (L == EIG3_SOA) {
@@ -213,8 +245,7 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Bod
         int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
 #if EIG3_PIPELINE
         // software pipeline: the loads of the lane's next matrix are issued
-        // before the arithmetic of the current one, so every wave keeps
-        // memory requests in flight while it computes
+        // before the arithmetic of the current one
         if (i >= n)
             return;
         Mat<T, S> cur;
@@ -225,7 +256,9 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Bod
             Mat<T, S> pre;
             if (more)
                 load_soa<T, S>(in, nxt, pre);
-            body(i, cur);
+            double o[KO];
+            body(i, cur, o);
+            store_rows(out, OL, i, o);
             if (!more)
                 break;
             cur = pre;
@@ -235,34 +268,55 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, Bod
         for (; i < n; i += stride) {
             Mat<T, S> m;
             load_soa<T, S>(in, i, m);
-            body(i, m);
+            double o[KO];
+            body(i, m, o);
+            store_rows(out, OL, i, o);
         }
 #endif
     } else if constexpr (EIG3_AOS_DIRECT) {
-        // each lane loads its own K consecutive values; the cache lines of a
-        // wave's contiguous span are shared by its K load instructions
+        // each lane loads its own K consecutive values
         const int64_t stride = int64_t(gridDim.x) * kBlock;
         for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
             Mat<T, S> m;
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 m.a[k] = ld(in.p[0] + K * i + k);
-            body(i, m);
+            double o[KO];
+            body(i, m, o);
+            store_rows(out, OL, i, o);
         }
     } else {
-        __shared__ AosTile<T, K> tile;
+        constexpr int kS = aos_stride<T, K>();
+        constexpr int kIn = kBlock * kS;
+        constexpr int kOut = OL == EIG3_AOS ? kBlock * KO : 0;
+        __shared__ __attribute__((aligned(16))) T tile[kIn > kOut ? kIn : kOut];
         const int64_t stride = int64_t(gridDim.x) * kBlock;
         for (int64_t first = int64_t(blockIdx.x) * kBlock; first < n; first += stride) {
-            __syncthreads(); // previous iteration's reads are done
+            __syncthreads(); // the previous iteration is done with the tile
             aos_stage<T, K>(in.p[0], first, n, tile);
             __syncthreads();
             const int64_t i = first + threadIdx.x;
-            if (i < n) {
+            const bool live = i < n;
+            double o[KO];
+            if (live) {
                 Mat<T, S> m;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    m.a[k] = tile.v[threadIdx.x * AosTile<T, K>::kStride + k];
-                body(i, m);
+                    m.a[k] = tile[threadIdx.x * kS + k];
+                body(i, m, o);
+            }
+            if constexpr (OL == EIG3_AOS) {
+                __syncthreads(); // every lane has read its input row
+                if (live) {
+#pragma unroll
+                    for (int e = 0; e < KO; ++e)
+                        tile[threadIdx.x * KO + e] = T(o[e]);
+                }
+                __syncthreads();
+                aos_flush<T, KO>(out.p[0], first, n, tile);
+            } else {
+                if (live)
+                    store_rows(out, EIG3_SOA, i, o);
             }
         }
     }
@@ -289,73 +343,83 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
 }
 
 // ------------------------------------------------------------------ kernels
-template <int S, int L, int Acc>
-EIG3_KERNEL void k_invariants_f64(int64_t n, In9<double> in, Out4<double> out)
+template <class T, int S, int L, int Acc>
+EIG3_KERNEL void k_invariants(int64_t n, In9<T> in, OutK<T, 4> out)
 {
-    for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
-        const Inv v = invariants_of<S, Acc>(m);
-        st(v.i1, out.p[0] + i);
-        st(v.j2, out.p[1] + i);
-        st(v.j3, out.p[2] + i);
-        st(v.disc, out.p[3] + i);
+    for_each_matrix<T, S, L, 4, EIG3_SOA>(n, in, out, [&](int64_t, const Mat<T, S> &m, double (&o)[4]) {
+        const auto v = invariants_of<S, Acc>(m);
+        o[0] = v.i1;
+        o[1] = v.j2;
+        o[2] = v.j3;
+        o[3] = v.disc;
     });
 }
 
-template <class T>
-__device__ __forceinline__ void store3(const Out3<T> &out, int layout, int64_t i, T l1, T l2, T l3)
+template <class T, int S, int L, int OL, int Acc>
+EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
 {
-    if (layout == EIG3_SOA) {
-        st(l1, out.p[0] + i);
-        st(l2, out.p[1] + i);
-        st(l3, out.p[2] + i);
+    for_each_matrix<T, S, L, 3, OL>(n, in, out, [&](int64_t, const Mat<T, S> &m, double (&o)[3]) {
+        const auto v = invariants_of<S, Acc>(m);
+        if constexpr (sizeof(T) == 8) {
+            eigvals_from_invariants(v, o[0], o[1], o[2]);
+        } else {
+            float l1, l2, l3;
+            eigvals_f32_from_invariants(v, l1, l2, l3);
+            o[0] = l1;
+            o[1] = l2;
+            o[2] = l3;
+        }
+    });
+}
+
+template <class T, int S> __device__ __forceinline__ Mat<double, S> widen(const Mat<T, S> &mt)
+{
+    Mat<double, S> m;
+#pragma unroll
+    for (int k = 0; k < Mat<T, S>::K; ++k)
+        m.a[k] = double(mt.a[k]);
+    return m;
+}
+
+template <int S> __device__ __forceinline__ Gen general_of(const Mat<double, S> &m)
+{
+    if constexpr (S == EIG3_GENERAL) {
+        return to_gen(m);
     } else {
-        T *o = out.p[0] + 3 * i;
-        st(l1, o);
-        st(l2, o + 1);
-        st(l3, o + 2);
+        const Sym y = to_sym(m);
+        return Gen{y.s00, y.s01, y.s02, y.s01, y.s11, y.s12, y.s02, y.s12, y.s22};
     }
 }
 
-template <int S, int L, int OL, int Acc>
-EIG3_KERNEL void k_eigvals_f64(int64_t n, In9<double> in, Out3<double> out)
+// full-matrix gradient -> the K outputs of the storage: general 9 entries;
+// symmetric: the derivative with respect to each stored entry (Stored) or
+// the components of the symmetric tensor derivative (Tensor)
+enum { kStored = 0, kTensor = 1 };
+template <int S, int Kind, int KO>
+__device__ __forceinline__ void gradient_rows(const double (&gr)[9], double (&o)[KO])
 {
-    for_each_matrix<double, S, L>(n, in, [&](int64_t i, const Mat<double, S> &m) {
-        const Inv v = invariants_of<S, Acc>(m);
-        double l1, l2, l3;
-        eigvals_from_invariants(v, l1, l2, l3);
-        store3(out, OL, i, l1, l2, l3);
-    });
-}
-
-template <int S, int L, int Acc>
-EIG3_KERNEL void k_invariants_f32(int64_t n, In9<float> in, Out4<float> out)
-{
-    for_each_matrix<float, S, L>(n, in, [&](int64_t i, const Mat<float, S> &m) {
-        const InvW v = invariants_of<S, Acc>(m);
-        st(float(v.i1), out.p[0] + i);
-        st(float(v.j2), out.p[1] + i);
-        st(float(v.j3), out.p[2] + i);
-        st(float(v.disc), out.p[3] + i);
-    });
-}
-
-template <int S, int L, int OL, int Acc>
-EIG3_KERNEL void k_eigvals_f32(int64_t n, In9<float> in, Out3<float> out)
-{
-    for_each_matrix<float, S, L>(n, in, [&](int64_t i, const Mat<float, S> &m) {
-        const InvW v = invariants_of<S, Acc>(m);
-        float l1, l2, l3;
-        eigvals_f32_from_invariants(v, l1, l2, l3);
-        store3(out, OL, i, l1, l2, l3);
-    });
+    if constexpr (S == EIG3_GENERAL) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            o[k] = gr[k];
+    } else {
+        const double h = Kind == kStored ? 1.0 : 0.5;
+        o[0] = gr[0];
+        o[1] = gr[4];
+        o[2] = gr[8];
+        o[3] = h * (gr[1] + gr[3]);
+        o[4] = h * (gr[2] + gr[6]);
+        o[5] = h * (gr[5] + gr[7]);
+    }
 }
 
 // The adjoint runs in binary64 for either storage type (binary32 entries and
 // upstream gradients are widened exactly; the result is rounded once).
 template <class T, int S, int L, int GL, int Acc>
-EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, Out9<T> out)
+EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, OutK<T, Mat<T, S>::K> out)
 {
-    for_each_matrix<T, S, L>(n, in, [&](int64_t i, const Mat<T, S> &mt) {
+    constexpr int KO = Mat<T, S>::K;
+    for_each_matrix<T, S, L, KO, L>(n, in, out, [&](int64_t i, const Mat<T, S> &mt, double (&o)[KO]) {
         double g1, g2, g3;
         if constexpr (GL == EIG3_SOA) {
             g1 = double(ld(g.p[0] + i));
@@ -366,126 +430,59 @@ EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, Out9<T> out)
             g2 = double(ld(g.p[0] + 3 * i + 1));
             g3 = double(ld(g.p[0] + 3 * i + 2));
         }
-        constexpr int K = Mat<T, S>::K;
-        Mat<double, S> m;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            m.a[k] = double(mt.a[k]);
+        const Mat<double, S> m = widen(mt);
         const Inv v = invariants_of<S, Acc>(m);
         const Coef c = backward_coefficients(v, g1, g2, g3);
         double gr[9];
-        if constexpr (S == EIG3_GENERAL) {
-            backward_general(to_gen(m), c, gr);
-        } else {
-            const Sym s = to_sym(m);
-            backward_general(Gen{s.s00, s.s01, s.s02, s.s01, s.s11, s.s12, s.s02, s.s12, s.s22}, c, gr);
-        }
-        double o[K];
-        if constexpr (S == EIG3_GENERAL) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                o[k] = gr[k];
-        } else {
-            // gradient with respect to the 6 stored entries
-            o[0] = gr[0];
-            o[1] = gr[4];
-            o[2] = gr[8];
-            o[3] = gr[1] + gr[3];
-            o[4] = gr[2] + gr[6];
-            o[5] = gr[5] + gr[7];
-        }
-        if constexpr (L == EIG3_SOA) {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                st(T(o[k]), out.p[k] + i);
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                st(T(o[k]), out.p[0] + K * i + k);
-        }
+        backward_general(general_of(m), c, gr);
+        gradient_rows<S, kStored>(gr, o);
     });
 }
 
 // Mohr-Coulomb yield function f and, if Grad, df/dsigma (binary64
 // arithmetic for either storage type).  For symmetric storage df/dsigma is
-// the tensor derivative: its 6 components (the off-diagonal value is that of
-// each of the two symmetric positions).
+// the tensor derivative: its 6 components.  Without the gradient f is the
+// single output slot; with it, f goes straight to its own array and the
+// slots carry the gradient in the layout of sigma.
 template <class T, int S, int L, int Acc, bool Grad>
-EIG3_KERNEL void k_mohr_coulomb(int64_t n, In9<T> in, double cf, double K, T *__restrict__ f, Out9<T> out)
+EIG3_KERNEL void k_mohr_coulomb(int64_t n, In9<T> in, double cf, double K, T *__restrict__ f,
+                                OutK<T, Grad ? Mat<T, S>::K : 1> out)
 {
-    for_each_matrix<T, S, L>(n, in, [&](int64_t i, const Mat<T, S> &mt) {
-        constexpr int KS = Mat<T, S>::K;
-        Mat<double, S> m;
-#pragma unroll
-        for (int k = 0; k < KS; ++k)
-            m.a[k] = double(mt.a[k]);
+    constexpr int KO = Grad ? Mat<T, S>::K : 1;
+    constexpr int OL = Grad ? L : EIG3_SOA;
+    for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](int64_t i, const Mat<T, S> &mt, double (&o)[KO]) {
+        const Mat<double, S> m = widen(mt);
         const Inv v = invariants_of<S, Acc>(m);
         // the gradient kernel carries many pointers: its coefficients are
         // immediates rather than SGPR-resident constants
         const MohrCoulomb mc = mohr_coulomb<!Grad>(v, cf, K);
-        st(T(mc.f), f + i);
         if constexpr (Grad) {
+            st(T(mc.f), f + i);
             const Coef c = backward_coefficients(mc.t, mc.g1, 0.0, mc.g3);
             double gr[9];
-            if constexpr (S == EIG3_GENERAL) {
-                backward_general(to_gen(m), c, gr);
-            } else {
-                const Sym y = to_sym(m);
-                backward_general(Gen{y.s00, y.s01, y.s02, y.s01, y.s11, y.s12, y.s02, y.s12, y.s22}, c, gr);
-            }
-            double o[KS];
-            if constexpr (S == EIG3_GENERAL) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    o[k] = gr[k];
-            } else {
-                o[0] = gr[0];
-                o[1] = gr[4];
-                o[2] = gr[8];
-                o[3] = 0.5 * (gr[1] + gr[3]);
-                o[4] = 0.5 * (gr[2] + gr[6]);
-                o[5] = 0.5 * (gr[5] + gr[7]);
-            }
-            if constexpr (L == EIG3_SOA) {
-#pragma unroll
-                for (int k = 0; k < KS; ++k)
-                    st(T(o[k]), out.p[k] + i);
-            } else {
-#pragma unroll
-                for (int k = 0; k < KS; ++k)
-                    st(T(o[k]), out.p[0] + KS * i + k);
-            }
+            backward_general(general_of(m), c, gr);
+            gradient_rows<S, kTensor>(gr, o);
+        } else {
+            o[0] = mc.f;
         }
     });
 }
 
-// Eigenprojectors E_1, E_2, E_3 (ascending eigenvalues); binary64
-// arithmetic for either storage type.  GENERAL: 9 entries per projector;
-// SYMMETRIC: the 6 stored components of each (symmetric) projector.  Output
-// slot 9k+e (general) or 6k+e (symmetric): SoA pointer per slot, or AoS with
-// 27 (18) values per matrix.
+// Eigenprojectors E_1, E_2, E_3 (ascending eigenvalues); binary64 arithmetic
+// for either storage type.  GENERAL: 9 entries per projector; SYMMETRIC: the
+// 6 components of each (symmetric) projector.  Slot 9k+e (general) or 6k+e
+// (symmetric).
 template <class T, int S, int L, int OL, int Acc>
-EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, Out27<T> out)
+EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::K> out)
 {
-    for_each_matrix<T, S, L>(n, in, [&](int64_t i, const Mat<T, S> &mt) {
-        constexpr int KS = Mat<T, S>::K;
-        Mat<double, S> m;
-#pragma unroll
-        for (int k = 0; k < KS; ++k)
-            m.a[k] = double(mt.a[k]);
+    constexpr int KS = Mat<T, S>::K;
+    constexpr int KO = 3 * KS;
+    for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](int64_t, const Mat<T, S> &mt, double (&o)[KO]) {
+        const Mat<double, S> m = widen(mt);
         const Inv v = invariants_of<S, Acc>(m);
         const Trig t = trig_from_invariants<false>(v);
-        Gen a;
-        if constexpr (S == EIG3_GENERAL) {
-            a = to_gen(m);
-        } else {
-            const Sym y = to_sym(m);
-            a = Gen{y.s00, y.s01, y.s02, y.s01, y.s11, y.s12, y.s02, y.s12, y.s22};
-        }
         double E[27];
-        eigenprojectors_general(a, t, E);
-        constexpr int NO = 3 * KS;
-        double o[NO];
+        eigenprojectors_general(general_of(m), t, E);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if constexpr (S == EIG3_GENERAL) {
@@ -500,15 +497,6 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, Out27<T> out)
                 o[6 * k + 4] = 0.5 * (E[9 * k + 2] + E[9 * k + 6]);
                 o[6 * k + 5] = 0.5 * (E[9 * k + 5] + E[9 * k + 7]);
             }
-        }
-        if constexpr (OL == EIG3_SOA) {
-#pragma unroll
-            for (int e = 0; e < NO; ++e)
-                st(T(o[e]), out.p[e] + i);
-        } else {
-#pragma unroll
-            for (int e = 0; e < NO; ++e)
-                st(T(o[e]), out.p[0] + NO * i + e);
         }
     });
 }
@@ -672,6 +660,15 @@ template <class F> void dispatch_sla4(int s, int l, int acc, F f)
 
 bool comparator(int acc) { return acc == EIG3_NAIVE || acc == EIG3_NAIVE_TENSOR; }
 
+template <class T, int KO> OutK<T, KO> out_slots(void *const *outs, int nout)
+{
+    OutK<T, KO> o;
+    for (int k = 0; k < KO; ++k)
+        o.p[k] = k < nout ? static_cast<T *>(outs[k]) : nullptr;
+    return o;
+}
+
+
 } // namespace
 
 // ===================================================================== C ABI
@@ -703,25 +700,22 @@ int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *
     void *outs[4] = {i1, j2, j3, disc};
     if ((st = check_outputs(A, outs, 4, size_t(A->n))) != EIG3_OK)
         return st;
+    if (A->dtype == EIG3_F32 && comparator(A->accuracy))
+        return EIG3_EUNSUPPORTED;
     const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
-    if (A->dtype == EIG3_F32) {
-        if (comparator(A->accuracy))
-            return EIG3_EUNSUPPORTED;
-        Out4<float> o32{{static_cast<float *>(i1), static_cast<float *>(j2), static_cast<float *>(j3),
-                         static_cast<float *>(disc)}};
-        const In9<float> in32 = inputs_of<float>(A);
-        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
-            hipLaunchKernelGGL((k_invariants_f32<S.value, L.value, Acc.value>), grid, block, 0, stream, A->n, in32,
-                               o32);
+    auto launch = [&](auto tag, auto dispatch) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(A);
+        const OutK<T, 4> out = out_slots<T, 4>(outs, 4);
+        dispatch(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            hipLaunchKernelGGL((k_invariants<T, S.value, L.value, Acc.value>), grid, block, 0, stream, A->n, in,
+                               out);
         });
-        return launched();
-    }
-    Out4<double> out{{static_cast<double *>(i1), static_cast<double *>(j2), static_cast<double *>(j3),
-                      static_cast<double *>(disc)}};
-    const In9<double> in = inputs_of<double>(A);
-    dispatch_sla4(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
-        hipLaunchKernelGGL((k_invariants_f64<S.value, L.value, Acc.value>), grid, block, 0, stream, A->n, in, out);
-    });
+    };
+    if (A->dtype == EIG3_F32)
+        launch(float{}, [](int s, int l, int acc, auto f) { dispatch_sla(s, l, acc, f); });
+    else
+        launch(double{}, [](int s, int l, int acc, auto f) { dispatch_sla4(s, l, acc, f); });
     return launched();
 }
 
@@ -738,32 +732,26 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
     const int nout = out_layout == EIG3_SOA ? 3 : 1;
     if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? 3 : 1))) != EIG3_OK)
         return st;
+    if (A->dtype == EIG3_F32 && comparator(A->accuracy))
+        return EIG3_EUNSUPPORTED;
     const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
-    if (A->dtype == EIG3_F32) {
-        if (comparator(A->accuracy))
-            return EIG3_EUNSUPPORTED;
-        Out3<float> o32{{static_cast<float *>(outs[0]), static_cast<float *>(outs[1]), static_cast<float *>(outs[2])}};
-        const In9<float> in32 = inputs_of<float>(A);
-        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+    auto launch = [&](auto tag, auto dispatch) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(A);
+        const OutK<T, 3> out = out_slots<T, 3>(outs, nout);
+        dispatch(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
             if (out_layout == EIG3_AOS)
-                hipLaunchKernelGGL((k_eigvals_f32<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream,
-                                   A->n, in32, o32);
+                hipLaunchKernelGGL((k_eigvals<T, S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream,
+                                   A->n, in, out);
             else
-                hipLaunchKernelGGL((k_eigvals_f32<S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream,
-                                   A->n, in32, o32);
+                hipLaunchKernelGGL((k_eigvals<T, S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream,
+                                   A->n, in, out);
         });
-        return launched();
-    }
-    Out3<double> out{{static_cast<double *>(outs[0]), static_cast<double *>(outs[1]), static_cast<double *>(outs[2])}};
-    const In9<double> in = inputs_of<double>(A);
-    dispatch_sla4(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
-        if (out_layout == EIG3_AOS)
-            hipLaunchKernelGGL((k_eigvals_f64<S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream, A->n,
-                               in, out);
-        else
-            hipLaunchKernelGGL((k_eigvals_f64<S.value, L.value, EIG3_SOA, Acc.value>), grid, block, 0, stream, A->n,
-                               in, out);
-    });
+    };
+    if (A->dtype == EIG3_F32)
+        launch(float{}, [](int s, int l, int acc, auto f) { dispatch_sla(s, l, acc, f); });
+    else
+        launch(double{}, [](int s, int l, int acc, auto f) { dispatch_sla4(s, l, acc, f); });
     return launched();
 }
 
@@ -806,10 +794,9 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
         const In9<T> in = inputs_of<T>(A);
         G3<T> gg{{static_cast<const T *>(g[0]), static_cast<const T *>(ng == 3 ? g[1] : nullptr),
                   static_cast<const T *>(ng == 3 ? g[2] : nullptr)}};
-        Out9<T> out;
-        for (int k = 0; k < 9; ++k)
-            out.p[k] = k < nout ? static_cast<T *>(outs[k]) : nullptr;
         dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            constexpr int KO = S.value == EIG3_GENERAL ? 9 : 6;
+            const OutK<T, KO> out = out_slots<T, KO>(outs, nout);
             if (g_layout == EIG3_AOS)
                 hipLaunchKernelGGL((k_backward<T, S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0, stream,
                                    A->n, in, gg, out);
@@ -864,17 +851,18 @@ int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f
     auto launch = [&](auto tag) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(sigma);
-        Out9<T> out;
-        for (int k = 0; k < 9; ++k)
-            out.p[k] = k < nout ? static_cast<T *>(outs[1 + k]) : nullptr;
         T *fo = static_cast<T *>(f);
         dispatch_sla4(sigma->structure, sigma->layout, sigma->accuracy, [&](auto S, auto L, auto Acc) {
-            if (grad)
+            constexpr int KS = S.value == EIG3_GENERAL ? 9 : 6;
+            if (grad) {
+                const OutK<T, KS> out = out_slots<T, KS>(outs + 1, nout);
                 hipLaunchKernelGGL((k_mohr_coulomb<T, S.value, L.value, Acc.value, true>), grid, block, 0, stream,
                                    sigma->n, in, cf, Kc, fo, out);
-            else
+            } else {
+                const OutK<T, 1> out = out_slots<T, 1>(outs, 1); // f is the only slot
                 hipLaunchKernelGGL((k_mohr_coulomb<T, S.value, L.value, Acc.value, false>), grid, block, 0,
                                    stream, sigma->n, in, cf, Kc, fo, out);
+            }
         });
     };
     if (sigma->dtype == EIG3_F32)
@@ -904,10 +892,9 @@ int eig3_eigenprojectors(const eig3_matrices *A, int32_t out_layout, void *const
     auto launch = [&](auto tag) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(A);
-        Out27<T> out;
-        for (int k = 0; k < 27; ++k)
-            out.p[k] = k < nout ? static_cast<T *>(outs[k]) : nullptr;
         dispatch_sla4(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            constexpr int KO = S.value == EIG3_GENERAL ? 27 : 18;
+            const OutK<T, KO> out = out_slots<T, KO>(outs, nout);
             if (out_layout == EIG3_AOS)
                 hipLaunchKernelGGL((k_eigenprojectors<T, S.value, L.value, EIG3_AOS, Acc.value>), grid, block, 0,
                                    stream, A->n, in, out);
