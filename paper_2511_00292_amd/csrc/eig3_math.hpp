@@ -243,17 +243,17 @@ __device__ __forceinline__ Inv invariants_symmetric_fma(const Sym &S)
     const double u12 = fma_(-b, d0d2, fma_(ac, d0, (q12 - q02) * b));
     const double u13 = fma_(b, d0d2, fma_(ac, d2, (q02 - q01) * b));
     const double u14 = fma_(d0d1, d2, fma_(-q01, d0, fma_(q02, d1, -q12 * d2)));
-    double s = u14 * u14;
-    s = fma_(2.0 * u13, u13, s);
-    s = fma_(2.0 * u12, u12, s);
-    s = fma_(2.0 * u11, u11, s);
-    s = fma_(2.0 * u10, u10, s);
-    s = fma_(2.0 * u9, u9, s);
-    s = fma_(2.0 * u8, u8, s);
-    s = fma_(14.0 * u4, u4, s);
-    s = fma_(14.0 * u3, u3, s);
-    s = fma_(14.0 * u2, u2, s);
-    r.disc = s;
+    // the squares grouped by weight; every partial sum is nonnegative
+    double s2 = u13 * u13;
+    s2 = fma_(u12, u12, s2);
+    s2 = fma_(u11, u11, s2);
+    s2 = fma_(u10, u10, s2);
+    s2 = fma_(u9, u9, s2);
+    s2 = fma_(u8, u8, s2);
+    double s14 = u4 * u4;
+    s14 = fma_(u3, u3, s14);
+    s14 = fma_(u2, u2, s14);
+    r.disc = fma_(14.0, s14, fma_(2.0, s2, u14 * u14));
     return r;
 }
 
@@ -472,6 +472,19 @@ template <> struct AngleConsts<float> {
     __device__ static float pi2() { return float(kPi2); }
 };
 
+// Quotient inside the arctangent, where den >= M, the larger operand.
+// binary64: correctly rounded division (any operand range).  binary32: the
+// caller scales the pair by a power of two so that M lies in [1/2, 1), hence
+// den in [1/2, 2): the hardware reciprocal (1 ulp) plus one residual
+// correction, with no range handling needed.
+__device__ __forceinline__ double quot_reduced(double num, double den) { return num / den; }
+__device__ __forceinline__ float quot_reduced(float num, float den)
+{
+    const float r = __builtin_amdgcn_rcpf(den);
+    const float q = num * r;
+    return fma_(fma_(-den, q, num), r, q);
+}
+
 template <bool Table = true, class T> __device__ __forceinline__ T atan2_nonneg(T y, T x)
 {
     const T m = y < x ? y : x;
@@ -480,7 +493,7 @@ template <bool Table = true, class T> __device__ __forceinline__ T atan2_nonneg(
     const T num = far ? m - M : m;
     const T den = far ? m + M : M;
     // 0/0 -> 0; a NaN operand fails the comparison and propagates
-    const T z = M == T(0) ? T(0) : num / den;
+    const T z = M == T(0) ? T(0) : quot_reduced(num, den);
     T r = z * atan_poly<Table>(z * z);
     r = far ? r + AngleConsts<T>::pi4() : r;
     return y > x ? AngleConsts<T>::pi2() - r : r;
@@ -683,13 +696,55 @@ struct InvW {
     double i1, j2, j3, disc; // binary64 values of the invariants
 };
 
+// J2, J3 and Delta depend on the matrix only through the diagonal
+// differences d0, d1, d2 and the off-diagonal entries (its deviatoric data).
+// The binary32 products below reach the third degree in those (J3 and the
+// factors of Delta), so taken as they are they overflow beyond about 2^42 and
+// lose accuracy to underflow below about 2^-42.  The data are therefore
+// scaled by one exact power of two that brings their largest magnitude into
+// [2^31, 2^32): every product then stays below 2^105, products of data down
+// to 2^-74 times the largest stay normal, and the invariants scale back
+// exactly in binary64 (J2 by 2^2s, J3 by 2^3s, Delta by 2^6s).  Powers of two
+// commute with every rounding in between.
+struct DevF32 {
+    float d0, d1, d2;
+    float o[6]; // general: A01 A02 A10 A12 A20 A21; symmetric: S01 S02 S12
+    int sc;     // the data are the matrix's times 2^-sc
+};
+
+template <int KO> __device__ __forceinline__ DevF32 dev_data_f32(float a00, float a11, float a22, const float *off)
+{
+    DevF32 v;
+    const float d[3] = {a00 - a11, a00 - a22, a11 - a22};
+    float m = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
+#pragma unroll
+    for (int k = 0; k < KO; ++k)
+        m = fmaxf(m, fabsf(off[k]));
+    v.sc = __builtin_amdgcn_frexp_expf(m) - 32; // frexp exponent 0 for 0, Inf, NaN
+    v.d0 = ldexpf(d[0], -v.sc);
+    v.d1 = ldexpf(d[1], -v.sc);
+    v.d2 = ldexpf(d[2], -v.sc);
+#pragma unroll
+    for (int k = 0; k < KO; ++k)
+        v.o[k] = ldexpf(off[k], -v.sc);
+    return v;
+}
+
+__device__ __forceinline__ void unscale(InvW &r, int sc)
+{
+    r.j2 = ldexp(r.j2, 2 * sc);
+    r.j3 = ldexp(r.j3, 3 * sc);
+    r.disc = ldexp(r.disc, 6 * sc);
+}
+
 __device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
 {
-    const float a00 = a[0], a01 = a[1], a02 = a[2], a10 = a[3], a11 = a[4], a12 = a[5], a20 = a[6], a21 = a[7],
-                a22 = a[8];
+    const float off[6] = {a[1], a[2], a[3], a[5], a[6], a[7]};
+    const DevF32 v = dev_data_f32<6>(a[0], a[4], a[8], off);
+    const float d0 = v.d0, d1 = v.d1, d2 = v.d2;
+    const float a01 = v.o[0], a02 = v.o[1], a10 = v.o[2], a12 = v.o[3], a20 = v.o[4], a21 = v.o[5];
     InvW r;
-    const float d0 = a00 - a11, d1 = a00 - a22, d2 = a11 - a22;
-    r.i1 = double((a00 + a11) + a22);
+    r.i1 = double((a[0] + a[4]) + a[8]);
     {
         const PairT<float> p01 = pair(a01, a10), p02 = pair(a02, a20), p12 = pair(a12, a21);
         const float sq = fma_(d0, d0, fma_(d1, d1, d2 * d2)) * (1.0f / 6.0f);
@@ -722,15 +777,17 @@ __device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
             disc = fma_(w[i] * (double(uh[i]) + double(ul[i])), double(vh[i]) + double(vl[i]), disc);
         r.disc = disc;
     }
+    unscale(r, v.sc);
     return r;
 }
 
 __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
 {
-    const float s00 = a[0], s11 = a[1], s22 = a[2], s01 = a[3], s02 = a[4], s12 = a[5];
+    const DevF32 v = dev_data_f32<3>(a[0], a[1], a[2], a + 3);
+    const float d0 = v.d0, d1 = v.d1, d2 = v.d2;
+    const float s01 = v.o[0], s02 = v.o[1], s12 = v.o[2];
     InvW r;
-    const float d0 = s00 - s11, d1 = s00 - s22, d2 = s11 - s22;
-    r.i1 = double((s00 + s11) + s22);
+    r.i1 = double((a[0] + a[1]) + a[2]);
     const float q01 = s01 * s01, q02 = s02 * s02, q12 = s12 * s12;
     // a sum of nonnegative terms: no compensation needed
     r.j2 = double(fma_(fma_(d0, d0, fma_(d1, d1, d2 * d2)), 1.0f / 6.0f, q01 + (q02 + q12)));
@@ -760,24 +817,37 @@ __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
         }
         r.disc = disc;
     }
+    unscale(r, v.sc);
     return r;
 }
 
 // Eigenvalues in binary32 from binary64 invariants.
 __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float &l1, float &l2, float &l3)
 {
-    const double disc = clamp0(v.disc);
-    const double y = sqrt(27.0 * disc);
+    // The angle pair (sqrt(27 Delta), 27 |J3|) is scaled by one exact power of
+    // two 2^-e so that its larger member lies in [1/2, 1): with x < 2^ex and
+    // 27 Delta < 2^ed, e = max(ex, ceil(ed / 2)).  The square root is then
+    // taken in binary32 on a value below 1 (in [1/4, 1) when it sets the
+    // scale; a smaller one only means a small angle), so the hardware square
+    // root (1 ulp) serves.
+    // A zero member takes no part in the choice (its frexp exponent, 0, would
+    // otherwise outvote a tiny partner and leave it subnormal in binary32).
+    const double d = 27.0 * clamp0(v.disc);
     const double x = 27.0 * fabs(v.j3);
-    // exact rescaling of the pair into binary32 range
-    const double big = fmax(fmax(y, x), 1e-300);
-    const int e = ilogb(big);
-    const float yf = float(ldexp(y, -e)), xf = float(ldexp(x, -e));
+    constexpr int kNone = -4096;
+    const int ex = x > 0.0 ? __builtin_amdgcn_frexp_exp(x) : kNone;
+    const int ed = d > 0.0 ? __builtin_amdgcn_frexp_exp(d) : kNone;
+    const int e = max(ex, (ed + 1) >> 1);
+    const float yf = __builtin_amdgcn_sqrtf(float(ldexp(d, -2 * e)));
+    const float xf = float(ldexp(x, -e));
     float psi = atan2_nonneg<false>(yf, xf);
     psi = v.j3 == v.j3 ? psi : float(v.j3); // NaN in J3 reaches the eigenvalues
     float s, c;
     sincos_sixth<false>(psi * (1.0f / 3.0f), s, c);
-    const float r = sqrtf(float(clamp0(v.j2) * kThird));
+    // r = sqrt(J2 / 3) the same way: q 2^-2k in [1/4, 1), r = sqrt(that) 2^k
+    const double q = clamp0(v.j2) * kThird;
+    const int k = (__builtin_amdgcn_frexp_exp(q) + 1) >> 1;
+    const float r = ldexpf(__builtin_amdgcn_sqrtf(float(ldexp(q, -2 * k))), k);
     const float mean = float(v.i1 * kThird);
     const float a1 = -r * fma_(float(kSqrt3), s, c);
     const float a2 = r * fma_(float(kSqrt3), s, -c);

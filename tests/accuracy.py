@@ -80,8 +80,12 @@ def lam_errors(t: Truth, lam) -> np.ndarray:
 def check(err: np.ndarray, bound: np.ndarray, allowance: np.ndarray | None = None, factor: float = 8.0,
           what: str = "") -> None:
     """Assert err <= factor * bound (+ allowance) elementwise, reporting the worst."""
+    err = np.asarray(err)
+    bound = np.broadcast_to(bound, err.shape)
+    if allowance is not None:
+        allowance = np.broadcast_to(allowance, err.shape)
     lim = factor * bound + (0.0 if allowance is None else allowance)
-    bad = err > lim
+    bad = ~(err <= lim)  # a NaN error fails the gate
     if bad.any():
         ratio = np.where(bound > 0, err / np.maximum(bound, 1e-300), np.inf)
         idx = np.unravel_index(np.argmax(np.where(bad, ratio, -1)), err.shape)
@@ -103,7 +107,7 @@ def check_g2(err: np.ndarray, bound: np.ndarray, err_paper: np.ndarray, factor: 
     rp = np.where(bound > 0, err_paper / tiny, np.where(err_paper > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
     lim = factor + 2.0 * rp.max(axis=0)
     worst = r.max(axis=0)
-    if np.any(worst > lim):
+    if not np.all(worst <= lim):  # a NaN error fails the gate
         raise AssertionError(f"{what}: worst ratio per output {np.round(worst, 2)} exceeds 8 + 2 x paper's "
                              f"worst {np.round(rp.max(axis=0), 2)}")
 

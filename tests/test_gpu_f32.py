@@ -96,3 +96,55 @@ def test_f32_backward(eig3, layout):
     gs = np.random.default_rng(3).standard_normal((1024, 3)).astype(np.float32)
     gsym = download_matrix(eig3.eig3_eigvals_backward(upload(s, layout), upload(gs, "soa"), "symmetric"), 6)
     assert np.isfinite(gsym[np.abs(gsym).max(1) < 1e30]).all()
+
+
+def _scaled_symmetric(k: int, n: int = 400, seed: int = 93) -> np.ndarray:
+    """Symmetric binary32 matrices scaled by 2^k (exact in binary32: every
+    entry stays a normal number): half random, half near a repeated root."""
+    rng = np.random.default_rng([seed, k + 1000])
+    s = 100.0 * rng.standard_normal((n, 6))
+    half = n // 2
+    s[half:, :3] = 100.0 * rng.standard_normal((n - half, 1))
+    s[half:] += 1e-2 * rng.standard_normal((n - half, 6))
+    s32 = (s * 2.0 ** k).astype(np.float32)
+    assert np.all(np.abs(s32) >= F32_TINY) and np.isfinite(s32).all()
+    return s32
+
+
+@pytest.mark.parametrize("acc", ACCS)
+@pytest.mark.parametrize("k", [-100, -60, 0, 60, 100])
+def test_f32_power_of_two_scales(eig3, acc, k):
+    """J2 and Delta span about 2^(2k) and 2^(6k) (far outside binary32 for
+    |k| >= 60); the square roots and the arctangent quotient run on values
+    brought back by exact powers of two, so the relative accuracy is the same
+    at every scale."""
+    s = _scaled_symmetric(k)
+    t = Truth(w.symmetric_to_general(s.astype(np.float64)), np.ones(s.shape[0]))
+    for layout in ("soa", "aos"):
+        lam = download_lam(eig3.eig3_eigvals(upload(s, layout), "symmetric", acc, "soa"))
+        check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"f32 scale 2^{k} {acc} {layout}")
+        assert np.all(np.diff(lam, axis=1) >= 0)
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_f32_special_matrices(eig3, acc):
+    """Zero, scaled identity (J2 = 0), exact double roots (Delta = 0), J3 = 0
+    at tiny and huge scales (Delta alone sets the angle), a scaled identity
+    with off-diagonal entries near 2^-51 (J3 near the binary32 subnormal
+    range, Delta = 0), and NaN in a diagonal or an off-diagonal entry (NaN in
+    that matrix only)."""
+    diag = [(0, 0, 0), (3, 3, 3), (1, 1, 2), (-2, 1, 1), (1, 2, 3), (-5e30, -5e30, 7e30),
+            (2.0 ** -100, 2.0 ** -99, 3 * 2.0 ** -100), (2.0 ** 100, 2.0 ** 101, 3 * 2.0 ** 100),
+            (97.2, 97.2, 97.2), (1, 2, 3), (4, 5, 6)]
+    g = np.zeros((len(diag), 9), dtype=np.float32)
+    for i, d in enumerate(diag):
+        g[i, 0], g[i, 4], g[i, 8] = d
+    off = np.float32(2.0 ** -51) * np.array([1.03, -1.88, 1.01], dtype=np.float32)
+    g[8, [1, 3]], g[8, [2, 6]], g[8, [5, 7]] = off[0], off[1], off[2]
+    g[9, 4] = np.nan
+    g[10, 5] = g[10, 7] = np.nan
+    lam = download_lam(eig3.eig3_eigvals(upload(g, "soa"), "general", acc, "soa"))
+    assert np.all(lam[0] == 0.0) and np.all(lam[1] == 3.0)
+    t = Truth(g[:9].astype(np.float64), np.ones(9))
+    check(lam_errors(t, lam[:9]), t.bound_lam(EPS32), what=f"f32 special matrices {acc}")
+    assert np.isnan(lam[9:]).all()
