@@ -32,19 +32,10 @@ constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 #ifndef EIG3_WAVES_PER_EU
 #define EIG3_WAVES_PER_EU 0
 #endif
-//  EIG3_PIPELINE      1: structure-of-arrays kernels loop over matrices with a
-//                     one-deep register prefetch; the grid is then sized to
-//                     EIG3_BLOCKS_PER_CU workgroups per compute unit
-#ifndef EIG3_PIPELINE
-#define EIG3_PIPELINE 0
-#endif
 //  EIG3_AOS_DIRECT    1: array-of-structures input is loaded lane by lane
 //                     instead of through the LDS tile
 #ifndef EIG3_AOS_DIRECT
 #define EIG3_AOS_DIRECT 0
-#endif
-#ifndef EIG3_BLOCKS_PER_CU
-#define EIG3_BLOCKS_PER_CU 4
 #endif
 #if EIG3_WAVES_PER_EU > 0
 #define EIG3_KERNEL __global__ __launch_bounds__(kBlock, EIG3_WAVES_PER_EU)
@@ -68,6 +59,60 @@ template <class T> __device__ __forceinline__ void st(T v, T *p)
 #else
     *p = v;
 #endif
+}
+
+// The workgroup's span of matrices [first, first + cnt) and this lane's place
+// in it.  Per-array accesses go through a buffer resource whose base is the
+// span's first row (wave-uniform, held in scalar registers) and whose size is
+// the span: a lane adds only a 32-bit offset, and the hardware range check
+// keeps every access inside the span (reads beyond it return 0 and writes
+// beyond it are dropped; the drivers below do not issue them anyway).
+struct Span {
+    int64_t first;
+    int cnt; // 1 .. kBlock
+    int lane;
+    __device__ bool live() const { return lane < cnt; }
+};
+
+__device__ __forceinline__ Span span_at(int64_t first, int64_t n)
+{
+    const int64_t rem = n - first;
+    return Span{first, rem < kBlock ? int(rem) : kBlock, int(threadIdx.x)};
+}
+
+// raw buffer, 32-bit data format: the gfx9-family descriptor word 3
+constexpr int kBufferWord3 = 0x00020000;
+// cache-policy operand: the nontemporal bit of gfx940-family memory operations
+constexpr int kBufferAux = EIG3_NONTEMPORAL ? 2 : 0;
+
+// rows of `per` values: the span's rows of array p
+template <class T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const T *p, const Span &s, int per)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p) + int64_t(per) * s.first, 0,
+                                             s.cnt * per * int(sizeof(T)), kBufferWord3);
+}
+
+using u32x2 = unsigned __attribute__((ext_vector_type(2)));
+
+// value c of the lane's row of `per` values
+template <class T> __device__ __forceinline__ T span_ld(const T *p, const Span &s, int per = 1, int c = 0)
+{
+    const __amdgpu_buffer_rsrc_t r = span_rsrc(p, s, per);
+    const int off = (s.lane * per + c) * int(sizeof(T));
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kBufferAux));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kBufferAux));
+}
+
+template <class T> __device__ __forceinline__ void span_st(T v, T *p, const Span &s, int per = 1, int c = 0)
+{
+    const __amdgpu_buffer_rsrc_t r = span_rsrc(p, s, per);
+    const int off = (s.lane * per + c) * int(sizeof(T));
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kBufferAux);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, kBufferAux);
 }
 
 template <class T> struct In9 {
@@ -175,11 +220,11 @@ template <class T> struct Mat<T, EIG3_SYMMETRIC> {
 };
 
 template <class T, int S>
-__device__ __forceinline__ void load_soa(const In9<T> &in, int64_t i, Mat<T, S> &m)
+__device__ __forceinline__ void load_soa(const In9<T> &in, const Span &sp, Mat<T, S> &m)
 {
 #pragma unroll
     for (int k = 0; k < Mat<T, S>::K; ++k)
-        m.a[k] = ld(in.p[k] + i);
+        m.a[k] = span_ld(in.p[k], sp);
 }
 
 __device__ __forceinline__ Gen to_gen(const Mat<double, EIG3_GENERAL> &m)
@@ -219,95 +264,69 @@ template <int S, int Acc> __device__ __forceinline__ Inv invariants_of(const Mat
 }
 
 template <class T, int KO>
-__device__ __forceinline__ void store_rows(const OutK<T, KO> &out, int layout, int64_t i, const double (&o)[KO])
+__device__ __forceinline__ void store_rows(const OutK<T, KO> &out, int layout, const Span &sp, const double (&o)[KO])
 {
     if (layout == EIG3_SOA) {
 #pragma unroll
         for (int e = 0; e < KO; ++e)
-            st(T(o[e]), out.p[e] + i);
+            span_st(T(o[e]), out.p[e], sp);
     } else {
 #pragma unroll
         for (int e = 0; e < KO; ++e)
-            st(T(o[e]), out.p[0] + KO * i + e);
+            span_st(T(o[e]), out.p[0], sp, KO, e);
     }
 }
 
-// Per-matrix driver shared by every kernel: loads matrix i (SoA pointers or
-// the LDS tile), calls body(i, matrix, o) which fills the KO output values
-// o[], and stores them in output layout OL.  For AoS input and AoS output the
-// rows go back through LDS and leave with 16-byte stores.
+// Per-matrix driver shared by every kernel: the grid strides over spans of
+// kBlock matrices; each lane loads its matrix (from the structure-of-arrays
+// arrays, or from the LDS tile for array-of-structures input), calls
+// body(span, matrix, o), which fills the KO output values o[], and stores them
+// in output layout OL.  For AoS input and AoS output the rows go back through
+// LDS and leave with 16-byte stores.
 template <class T, int S, int L, int KO, int OL, class Body>
 __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, const OutK<T, KO> &out, Body body)
 {
     constexpr int K = Mat<T, S>::K;
-    if constexpr (L == EIG3_SOA) {
-        const int64_t stride = int64_t(gridDim.x) * kBlock;
-        int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-#if EIG3_PIPELINE
-        // software pipeline: the loads of the lane's next matrix are issued
-        // before the arithmetic of the current one
-        if (i >= n)
-            return;
-        Mat<T, S> cur;
-        load_soa<T, S>(in, i, cur);
-        for (;;) {
-            const int64_t nxt = i + stride;
-            const bool more = nxt < n;
-            Mat<T, S> pre;
-            if (more)
-                load_soa<T, S>(in, nxt, pre);
-            double o[KO];
-            body(i, cur, o);
-            store_rows(out, OL, i, o);
-            if (!more)
-                break;
-            cur = pre;
-            i = nxt;
-        }
-#else
-        for (; i < n; i += stride) {
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    if constexpr (L == EIG3_SOA || EIG3_AOS_DIRECT) {
+        for (int64_t first = int64_t(blockIdx.x) * kBlock; first < n; first += stride) {
+            const Span sp = span_at(first, n);
+            if (!sp.live())
+                continue;
             Mat<T, S> m;
-            load_soa<T, S>(in, i, m);
-            double o[KO];
-            body(i, m, o);
-            store_rows(out, OL, i, o);
-        }
-#endif
-    } else if constexpr (EIG3_AOS_DIRECT) {
-        // each lane loads its own K consecutive values
-        const int64_t stride = int64_t(gridDim.x) * kBlock;
-        for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-            Mat<T, S> m;
+            if constexpr (L == EIG3_SOA) {
+                load_soa<T, S>(in, sp, m);
+            } else {
+                // each lane loads its own K consecutive values
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                m.a[k] = ld(in.p[0] + K * i + k);
+                for (int k = 0; k < K; ++k)
+                    m.a[k] = span_ld(in.p[0], sp, K, k);
+            }
             double o[KO];
-            body(i, m, o);
-            store_rows(out, OL, i, o);
+            body(sp, m, o);
+            store_rows(out, OL, sp, o);
         }
     } else {
         constexpr int kS = aos_stride<T, K>();
         constexpr int kIn = kBlock * kS;
         constexpr int kOut = OL == EIG3_AOS ? kBlock * KO : 0;
         __shared__ __attribute__((aligned(16))) T tile[kIn > kOut ? kIn : kOut];
-        const int64_t stride = int64_t(gridDim.x) * kBlock;
         for (int64_t first = int64_t(blockIdx.x) * kBlock; first < n; first += stride) {
             __syncthreads(); // the previous iteration is done with the tile
             aos_stage<T, K>(in.p[0], first, n, tile);
             __syncthreads();
-            const int64_t i = first + threadIdx.x;
-            const bool live = i < n;
+            const Span sp = span_at(first, n);
             double o[KO];
-            if (live) {
+            if (sp.live()) {
                 Mat<T, S> m;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
                     m.a[k] = tile[threadIdx.x * kS + k];
-                body(i, m, o);
+                body(sp, m, o);
             }
             if constexpr (OL == EIG3_AOS) {
                 __syncthreads(); // every lane has read its input row
-                if (live) {
+                if (sp.live()) {
 #pragma unroll
                     for (int e = 0; e < KO; ++e)
                         tile[threadIdx.x * KO + e] = T(o[e]);
@@ -315,8 +334,8 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, con
                 __syncthreads();
                 aos_flush<T, KO>(out.p[0], first, n, tile);
             } else {
-                if (live)
-                    store_rows(out, EIG3_SOA, i, o);
+                if (sp.live())
+                    store_rows(out, EIG3_SOA, sp, o);
             }
         }
     }
@@ -346,7 +365,7 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
 template <class T, int S, int L, int Acc>
 EIG3_KERNEL void k_invariants(int64_t n, In9<T> in, OutK<T, 4> out)
 {
-    for_each_matrix<T, S, L, 4, EIG3_SOA>(n, in, out, [&](int64_t, const Mat<T, S> &m, double (&o)[4]) {
+    for_each_matrix<T, S, L, 4, EIG3_SOA>(n, in, out, [&](const Span &, const Mat<T, S> &m, double (&o)[4]) {
         const auto v = invariants_of<S, Acc>(m);
         o[0] = v.i1;
         o[1] = v.j2;
@@ -358,7 +377,7 @@ EIG3_KERNEL void k_invariants(int64_t n, In9<T> in, OutK<T, 4> out)
 template <class T, int S, int L, int OL, int Acc>
 EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
 {
-    for_each_matrix<T, S, L, 3, OL>(n, in, out, [&](int64_t, const Mat<T, S> &m, double (&o)[3]) {
+    for_each_matrix<T, S, L, 3, OL>(n, in, out, [&](const Span &, const Mat<T, S> &m, double (&o)[3]) {
         const auto v = invariants_of<S, Acc>(m);
         if constexpr (sizeof(T) == 8) {
             eigvals_from_invariants(v, o[0], o[1], o[2]);
@@ -419,16 +438,16 @@ template <class T, int S, int L, int GL, int Acc>
 EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, OutK<T, Mat<T, S>::K> out)
 {
     constexpr int KO = Mat<T, S>::K;
-    for_each_matrix<T, S, L, KO, L>(n, in, out, [&](int64_t i, const Mat<T, S> &mt, double (&o)[KO]) {
+    for_each_matrix<T, S, L, KO, L>(n, in, out, [&](const Span &sp, const Mat<T, S> &mt, double (&o)[KO]) {
         double g1, g2, g3;
         if constexpr (GL == EIG3_SOA) {
-            g1 = double(ld(g.p[0] + i));
-            g2 = double(ld(g.p[1] + i));
-            g3 = double(ld(g.p[2] + i));
+            g1 = double(span_ld(g.p[0], sp));
+            g2 = double(span_ld(g.p[1], sp));
+            g3 = double(span_ld(g.p[2], sp));
         } else {
-            g1 = double(ld(g.p[0] + 3 * i));
-            g2 = double(ld(g.p[0] + 3 * i + 1));
-            g3 = double(ld(g.p[0] + 3 * i + 2));
+            g1 = double(span_ld(g.p[0], sp, 3, 0));
+            g2 = double(span_ld(g.p[0], sp, 3, 1));
+            g3 = double(span_ld(g.p[0], sp, 3, 2));
         }
         const Mat<double, S> m = widen(mt);
         const Inv v = invariants_of<S, Acc>(m);
@@ -450,14 +469,14 @@ EIG3_KERNEL void k_mohr_coulomb(int64_t n, In9<T> in, double cf, double K, T *__
 {
     constexpr int KO = Grad ? Mat<T, S>::K : 1;
     constexpr int OL = Grad ? L : EIG3_SOA;
-    for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](int64_t i, const Mat<T, S> &mt, double (&o)[KO]) {
+    for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](const Span &sp, const Mat<T, S> &mt, double (&o)[KO]) {
         const Mat<double, S> m = widen(mt);
         const Inv v = invariants_of<S, Acc>(m);
         // the gradient kernel carries many pointers: its coefficients are
         // immediates rather than SGPR-resident constants
         const MohrCoulomb mc = mohr_coulomb<!Grad>(v, cf, K);
         if constexpr (Grad) {
-            st(T(mc.f), f + i);
+            span_st(T(mc.f), f, sp);
             const Coef c = backward_coefficients(mc.t, mc.g1, 0.0, mc.g3);
             double gr[9];
             backward_general(general_of(m), c, gr);
@@ -477,7 +496,7 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
 {
     constexpr int KS = Mat<T, S>::K;
     constexpr int KO = 3 * KS;
-    for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](int64_t, const Mat<T, S> &mt, double (&o)[KO]) {
+    for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](const Span &, const Mat<T, S> &mt, double (&o)[KO]) {
         const Mat<double, S> m = widen(mt);
         const Inv v = invariants_of<S, Acc>(m);
         const Trig t = trig_from_invariants<false>(v);
@@ -502,32 +521,11 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
 }
 
 // ------------------------------------------------------------------- host
-int device_cus()
-{
-    // compute units of the current device, queried once per device
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
-        return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        cached[dev] = cus;
-    }
-    return cached[dev];
-}
-
 int64_t grid_for(int64_t n, int layout)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
-    int64_t cap = kMaxBlocks;
-#if EIG3_PIPELINE
-    if (layout == EIG3_SOA)
-        cap = int64_t(device_cus()) * EIG3_BLOCKS_PER_CU;
-#endif
     (void)layout;
-    return b < cap ? b : cap;
+    return b < kMaxBlocks ? b : kMaxBlocks;
 }
 
 bool valid_enum(int v, int hi) { return v >= 0 && v <= hi; }
