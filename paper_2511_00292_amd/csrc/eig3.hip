@@ -162,18 +162,33 @@ __device__ __forceinline__ void aos_stage(const T *__restrict__ base, int64_t fi
     if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
         using V = typename Vec16<T>::type;
         constexpr int NV = Vec16<T>::N;
+        // a full span is kBlock*K/NV vectors: at most kPer per lane, all
+        // loads issued before the first LDS write (one memory round trip)
+        constexpr int kPer = (kBlock * K / NV + kBlock - 1) / kBlock;
         const int nvec = count / NV;
         const V *vsrc = reinterpret_cast<const V *>(src);
-        for (int v = threadIdx.x; v < nvec; v += kBlock) {
-            const V x = ld(vsrc + v);
-            if constexpr (kS == K) {
-                // unpadded rows: the tile is the span itself
-                reinterpret_cast<V *>(tile)[v] = x;
-            } else {
+        if (nvec > 0) {
+            // branch-free loads: a lane past the end reloads the last vector
+            V x[kPer];
 #pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    const int e = v * NV + j, m = e / K, k = e - m * K;
-                    tile[m * kS + k] = x[j];
+            for (int r = 0; r < kPer; ++r) {
+                const int v = int(threadIdx.x) + r * kBlock;
+                x[r] = ld(vsrc + (v < nvec ? v : nvec - 1));
+            }
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const int v = int(threadIdx.x) + r * kBlock;
+                if (v < nvec) {
+                    if constexpr (kS == K) {
+                        // unpadded rows: the tile is the span itself
+                        reinterpret_cast<V *>(tile)[v] = x[r];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < NV; ++j) {
+                            const int e = v * NV + j, m = e / K, k = e - m * K;
+                            tile[m * kS + k] = x[r][j];
+                        }
+                    }
                 }
             }
         }
@@ -201,8 +216,21 @@ __device__ __forceinline__ void aos_flush(T *__restrict__ base, int64_t first, i
         const int nvec = count / NV;
         V *vdst = reinterpret_cast<V *>(dst);
         const V *vtile = reinterpret_cast<const V *>(tile);
-        for (int v = threadIdx.x; v < nvec; v += kBlock)
-            st(vtile[v], vdst + v);
+        constexpr int kPer = (kBlock * KO / NV + kBlock - 1) / kBlock;
+        if (nvec > 0) {
+            V x[kPer];
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const int v = int(threadIdx.x) + r * kBlock;
+                x[r] = vtile[v < nvec ? v : nvec - 1];
+            }
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const int v = int(threadIdx.x) + r * kBlock;
+                if (v < nvec)
+                    st(x[r], vdst + v);
+            }
+        }
         done = nvec * NV;
     }
     for (int e = done + threadIdx.x; e < count; e += kBlock)
