@@ -1,8 +1,10 @@
 // eig3.hip -- kernels and C ABI of libeig3 (see include/eig3.h).
 //
-// Execution model: one 3x3 matrix per lane, wave64, 256-lane workgroups,
-// grid-stride loop over a 64-bit matrix index.  Structure-of-arrays inputs
-// give one fully coalesced 8-byte load per entry and lane; array-of-structures
+// Execution model: one 3x3 matrix per lane, wave64, 256-lane workgroups; the
+// grid strides over spans of 256 consecutive matrices (one launch normally
+// covers the batch with one span per workgroup).  Structure-of-arrays inputs
+// are read with one coalesced buffer load per entry and lane (a scalar buffer
+// resource per array over the span, 32-bit lane offsets); array-of-structures
 // inputs are staged through LDS by the workgroup with 16-byte loads and then
 // read back one matrix per lane.  Nothing here is a dense contraction, so
 // there is no MFMA: the kernels are HBM-bandwidth bound with a binary64 VALU
