@@ -96,19 +96,25 @@ def check(err: np.ndarray, bound: np.ndarray, allowance: np.ndarray | None = Non
 
 
 def check_g2(err: np.ndarray, bound: np.ndarray, err_paper: np.ndarray, factor: float = 8.0,
-             what: str = "") -> None:
-    """G2 per output column: worst ratio of x no worse than 8 + 2x the worst
-    ratio of the paper's algorithm over the same bucket."""
+             what: str = "", pool: bool = False) -> None:
+    """G2: the worst ratio err / bound of x over a bucket is no worse than
+    8 + 2x the worst ratio of the paper's algorithm over the same bucket.
+    Per output column, or, with pool=True, over all columns together (the
+    three eigenvalues of a bucket: at kappa(V) > 10 their worst ratios are
+    heavy-tailed extremes whose position among the three carries no
+    information)."""
     bound = np.broadcast_to(bound, err.shape)
     if err.size == 0:
         return
     tiny = np.maximum(bound, 1e-300)
     r = np.where(bound > 0, err / tiny, np.where(err > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
     rp = np.where(bound > 0, err_paper / tiny, np.where(err_paper > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
+    if pool:
+        r, rp = r.reshape(-1, 1), rp.reshape(-1, 1)
     lim = factor + 2.0 * rp.max(axis=0)
     worst = r.max(axis=0)
     if not np.all(worst <= lim):  # a NaN error fails the gate
-        raise AssertionError(f"{what}: worst ratio per output {np.round(worst, 2)} exceeds 8 + 2 x paper's "
+        raise AssertionError(f"{what}: worst ratio {np.round(worst, 2)} exceeds 8 + 2 x paper's "
                              f"worst {np.round(rp.max(axis=0), 2)}")
 
 

@@ -84,7 +84,7 @@ def test_config2_buckets(eig3, plain, c2, acc, kappa):
     if kappa <= 10.0:
         check(el, np.broadcast_to(bl, el.shape), what=f"config2 eigvals kappa={kappa} {acc} (G1)")
     else:
-        check_g2(el, bl, al, what=f"config2 eigvals kappa={kappa} {acc} (G2)")
+        check_g2(el, bl, al, what=f"config2 eigvals kappa={kappa} {acc} (G2)", pool=True)
     if kappa == 1.0 or (kappa == 10.0 and acc == "compensated"):
         check(ei, bi, what=f"config2 invariants kappa={kappa} {acc} (G1)")
     else:
@@ -112,7 +112,7 @@ def test_config5_forward(eig3, plain, c5, acc):
     well = c["kappa"] <= 10
     check(el[well], bl[well], what=f"config5 eigvals kappa<=10 {acc} (G1)")
     al = lam_errors(t, plain.eigvals(c["a"]))
-    check_g2(el[~well], bl[~well], al[~well], what=f"config5 eigvals kappa>10 {acc} (G2)")
+    check_g2(el[~well], bl[~well], al[~well], what=f"config5 eigvals kappa>10 {acc} (G2)", pool=True)
 
 
 @pytest.mark.parametrize("acc", ACCS)
