@@ -21,7 +21,8 @@
  *    on `stream` (a hipStream_t; NULL = the default stream) and returns.
  *  - Inputs are read-only.  Outputs must not alias inputs or each other.
  *  - n == 0 is a no-op returning EIG3_OK.  Invalid arguments (NULL pointers,
- *    n < 0, unknown enum values, outputs aliasing inputs) return EIG3_EINVAL
+ *    pointers not aligned to the element size, n < 0 or n > 2^56, unknown
+ *    enum values, outputs aliasing inputs or each other) return EIG3_EINVAL
  *    and launch nothing.  A failed launch returns EIG3_ELAUNCH.
  *  - Precondition (not checked): real, diagonalizable input with real
  *    spectrum.  Outside it the results stay finite for finite input: J2 < 0
@@ -104,7 +105,7 @@ typedef enum eig3_accuracy {
 
 /* A batch of n matrices resident in device memory. */
 typedef struct eig3_matrices {
-    int64_t n;         /* number of matrices, n >= 0 */
+    int64_t n;         /* number of matrices, 0 <= n <= 2^56 */
     int32_t dtype;     /* eig3_dtype */
     int32_t structure; /* eig3_structure */
     int32_t layout;    /* eig3_layout */

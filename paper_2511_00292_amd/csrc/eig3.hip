@@ -551,12 +551,16 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
 }
 
 // ------------------------------------------------------------------- host
-int64_t grid_for(int64_t n, int layout)
+// one workgroup per span of kBlock matrices, up to kMaxBlocks (the grid
+// strides beyond that)
+int64_t grid_for(int64_t n)
 {
-    int64_t b = (n + kBlock - 1) / kBlock;
-    (void)layout;
+    const int64_t b = (n + kBlock - 1) / kBlock;
     return b < kMaxBlocks ? b : kMaxBlocks;
 }
+
+// largest batch: keeps every operand's byte size far inside size_t
+constexpr int64_t kMaxMatrices = int64_t(1) << 56;
 
 bool valid_enum(int v, int hi) { return v >= 0 && v <= hi; }
 
@@ -587,7 +591,7 @@ bool aligned(const void *p, size_t a) { return (uintptr_t(p) % a) == 0; }
 // common validation of the matrix batch; K = number of stored entries
 int check_matrices(const eig3_matrices *A)
 {
-    if (A == nullptr || A->n < 0)
+    if (A == nullptr || A->n < 0 || A->n > kMaxMatrices)
         return EIG3_EINVAL;
     if (!valid_enum(A->dtype, 1) || !valid_enum(A->structure, 1) || !valid_enum(A->layout, 1) ||
         !valid_enum(A->accuracy, 3))
@@ -730,7 +734,7 @@ int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *
         return st;
     if (A->dtype == EIG3_F32 && comparator(A->accuracy))
         return EIG3_EUNSUPPORTED;
-    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
     auto launch = [&](auto tag, auto dispatch) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(A);
@@ -762,7 +766,7 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
         return st;
     if (A->dtype == EIG3_F32 && comparator(A->accuracy))
         return EIG3_EUNSUPPORTED;
-    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
     auto launch = [&](auto tag, auto dispatch) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(A);
@@ -816,7 +820,7 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
                 return EIG3_EINVAL;
         }
     }
-    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
     auto launch = [&](auto tag) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(A);
@@ -875,7 +879,7 @@ int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f
     }
     const double cf = (m + 1.0) / (2.0 * s_yc);
     const double Kc = (m - 1.0) / (m + 1.0);
-    const dim3 grid(unsigned(grid_for(sigma->n, sigma->layout))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(sigma->n))), block(kBlock);
     auto launch = [&](auto tag) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(sigma);
@@ -916,7 +920,7 @@ int eig3_eigenprojectors(const eig3_matrices *A, int32_t out_layout, void *const
         outs[k] = E[k];
     if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? 3 * K : 1))) != EIG3_OK)
         return st;
-    const dim3 grid(unsigned(grid_for(A->n, A->layout))), block(kBlock);
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
     auto launch = [&](auto tag) {
         using T = decltype(tag);
         const In9<T> in = inputs_of<T>(A);

@@ -61,6 +61,7 @@ def _eigvals(lib, m, outs=(0x9000000, 0xA000000, 0xB000000), out_layout=0):
 def test_null_and_bad_enums_rejected(lib):
     assert lib.eig3_eigvals(None, 0, (ctypes.c_void_p * 3)(1, 2, 3), None) == capi.EIG3_EINVAL
     assert _eigvals(lib, _mat(n=-1)) == capi.EIG3_EINVAL
+    assert _eigvals(lib, _mat(n=(1 << 56) + 1)) == capi.EIG3_EINVAL     # beyond the largest batch
     assert _eigvals(lib, _mat(dtype=7)) == capi.EIG3_EINVAL
     assert _eigvals(lib, _mat(structure=3)) == capi.EIG3_EINVAL
     assert _eigvals(lib, _mat(layout=2)) == capi.EIG3_EINVAL
