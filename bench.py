@@ -37,6 +37,8 @@ BYTES = {
     "fwd_symmetric_f32": 6 * 4 + 3 * 4,
     "fwd_general_f32": 9 * 4 + 3 * 4,
     "bwd_general_f64": 9 * 8 + 3 * 8 + 9 * 8,
+    "bwd_general_f32": 9 * 4 + 3 * 4 + 9 * 4,
+    "step_general_f32": (9 * 4 + 3 * 4) + (9 * 4 + 3 * 4 + 9 * 4),
     "mohr_coulomb_symmetric_f64": 6 * 8 + 8 + 6 * 8,
     "eigenprojectors_general_f64": 9 * 8 + 27 * 8,
 }
@@ -300,7 +302,25 @@ def main():
         lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)
         variant("config5 fwd general f64 fma aos", "fwd_general_f64", N_MAIN,
                 lambda: eig3.eig3_eigvals(a_aos, "general", "fma", "aos", out=lam_aos), "f64")
-        del a, g, lam, grad, a_aos, lam_aos
+        del a_aos, lam_aos
+        # the same workload stored in binary32: forward in both evaluations,
+        # the adjoint (binary64 arithmetic, rounded once), and the whole step
+        a32 = [t.float() for t in a]
+        g32 = [t.float() for t in g]
+        lam32 = [torch.empty(N_MAIN, dtype=torch.float32, device=dev) for _ in range(3)]
+        grad32 = [torch.empty(N_MAIN, dtype=torch.float32, device=dev) for _ in range(9)]
+        for acc_v in ("fma", "compensated"):
+            variant(f"config5 fwd general f32 {acc_v}", "fwd_general_f32", N_MAIN,
+                    lambda acc_v=acc_v: eig3.eig3_eigvals(a32, "general", acc_v, "soa", out=lam32), "f32")
+        variant("config5 bwd general f32", "bwd_general_f32", N_MAIN,
+                lambda: eig3.eig3_eigvals_backward(a32, g32, "general", "fma", out=grad32), "f32")
+
+        for acc_v in ("fma", "compensated"):
+            def step32(acc_v=acc_v):
+                eig3.eig3_eigvals(a32, "general", acc_v, "soa", out=lam32)
+                eig3.eig3_eigvals_backward(a32, g32, "general", "fma", out=grad32)
+            variant(f"config5 step f32 ({acc_v} forward + adjoint)", "step_general_f32", N_MAIN, step32, "f32")
+        del a, g, lam, grad, a32, g32, lam32, grad32
         torch.cuda.empty_cache()
         # perturbation sweep (config 2)
         t0 = time.perf_counter()
