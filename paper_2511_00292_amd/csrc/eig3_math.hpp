@@ -54,6 +54,17 @@ template <class T> __device__ __forceinline__ PairT<T> pair(T a, T b)
     two_prod(a, b, p.hi, p.lo);
     return p;
 }
+// k*x*y for a small integer constant k, kept exactly as hi + lo: the pair
+// product x*y is exact, k*hi is split exactly by TwoProduct, and k*lo adds a
+// rounding of order eps^2 |k x y| (rounding k*x first would cost eps |k x y|)
+template <class T> __device__ __forceinline__ PairT<T> pair_scaled(T k, T x, T y)
+{
+    const PairT<T> p = pair(x, y);
+    PairT<T> r;
+    two_prod(k, p.hi, r.hi, r.lo);
+    r.lo = fma_(k, p.lo, r.lo);
+    return r;
+}
 template <class T> __device__ __forceinline__ PairT<T> neg(PairT<T> p) { return PairT<T>{-p.hi, -p.lo}; }
 using Pair = PairT<double>;
 
@@ -311,12 +322,20 @@ __device__ __forceinline__ double sum_wuv_comp(const double uh[14], const double
     }
 #pragma unroll
     for (int i = 1; i < 14; ++i) {
-        double p, pe, wp, wpe, t, te;
+        double p, pe, t, te;
         two_prod(uh[i], vh[i], p, pe);
-        two_prod(w[i], p, wp, wpe);
-        two_sum(s, wp, t, te);
+        const double corr = fma_(uh[i], vl[i], fma_(ul[i], vh[i], pe));
+        if (w[i] == 8.0 || w[i] == 2.0 || w[i] == 1.0) {
+            // a power of two scales exactly
+            two_sum(s, w[i] * p, t, te);
+            c = c + fma_(w[i], corr, te);
+        } else {
+            double wp, wpe;
+            two_prod(w[i], p, wp, wpe);
+            two_sum(s, wp, t, te);
+            c = c + (te + fma_(w[i], corr, wpe));
+        }
         s = t;
-        c = c + (te + fma_(w[i], fma_(uh[i], vl[i], fma_(ul[i], vh[i], pe)), wpe));
     }
     return s + c;
 }
@@ -343,11 +362,11 @@ __device__ __forceinline__ Inv invariants_general_comp(const Gen &A)
     {
         const double t1 = g.d1 + g.d2, t2 = g.d0 - g.d2, t3 = -g.d0 - g.d1;
         Acc a;
-        a.first(pair(27.0 * A.a01, A.a12), A.a20);
-        a.add(pair(27.0 * A.a02, A.a10), A.a21);
-        a.add(pair(9.0 * A.a01, A.a10), t1);
-        a.add(pair(9.0 * A.a02, A.a20), t2);
-        a.add(pair(9.0 * A.a12, A.a21), t3);
+        a.first(pair_scaled(27.0, A.a01, A.a12), A.a20);
+        a.add(pair_scaled(27.0, A.a02, A.a10), A.a21);
+        a.add(pair_scaled(9.0, A.a01, A.a10), t1);
+        a.add(pair_scaled(9.0, A.a02, A.a20), t2);
+        a.add(pair_scaled(9.0, A.a12, A.a21), t3);
         a.add(pair(-t1, t2), t3);
         r.j3 = a.value() * kTwentySeventh;
     }
@@ -375,10 +394,10 @@ __device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
     {
         const double t1 = g.d1 + g.d2, t2 = g.d0 - g.d2, t3 = -g.d0 - g.d1;
         Acc a;
-        a.first(pair(54.0 * S.s01, S.s12), S.s02);
-        a.add(pair(9.0 * S.s01, S.s01), t1);
-        a.add(pair(9.0 * S.s02, S.s02), t2);
-        a.add(pair(9.0 * S.s12, S.s12), t3);
+        a.first(pair_scaled(54.0, S.s01, S.s12), S.s02);
+        a.add(pair_scaled(9.0, S.s01, S.s01), t1);
+        a.add(pair_scaled(9.0, S.s02, S.s02), t2);
+        a.add(pair_scaled(9.0, S.s12, S.s12), t3);
         a.add(pair(-t1, t2), t3);
         r.j3 = a.value() * kTwentySeventh;
     }
@@ -757,11 +776,11 @@ __device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
     {
         const float t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
         AccT<float> acc;
-        acc.first(pair(27.0f * a01, a12), a20);
-        acc.add(pair(27.0f * a02, a10), a21);
-        acc.add(pair(9.0f * a01, a10), t1);
-        acc.add(pair(9.0f * a02, a20), t2);
-        acc.add(pair(9.0f * a12, a21), t3);
+        acc.first(pair_scaled(27.0f, a01, a12), a20);
+        acc.add(pair_scaled(27.0f, a02, a10), a21);
+        acc.add(pair_scaled(9.0f, a01, a10), t1);
+        acc.add(pair_scaled(9.0f, a02, a20), t2);
+        acc.add(pair_scaled(9.0f, a12, a21), t3);
         acc.add(pair(-t1, t2), t3);
         r.j3 = (double(acc.s) + double(acc.c)) * kTwentySeventh;
     }
@@ -794,10 +813,10 @@ __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
     {
         const float t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
         AccT<float> acc;
-        acc.first(pair(54.0f * s01, s12), s02);
-        acc.add(pair(9.0f * s01, s01), t1);
-        acc.add(pair(9.0f * s02, s02), t2);
-        acc.add(pair(9.0f * s12, s12), t3);
+        acc.first(pair_scaled(54.0f, s01, s12), s02);
+        acc.add(pair_scaled(9.0f, s01, s01), t1);
+        acc.add(pair_scaled(9.0f, s02, s02), t2);
+        acc.add(pair_scaled(9.0f, s12, s12), t3);
         acc.add(pair(-t1, t2), t3);
         r.j3 = (double(acc.s) + double(acc.c)) * kTwentySeventh;
     }
