@@ -54,6 +54,23 @@ def _check_device_tensor(t: torch.Tensor, what: str) -> None:
         raise ValueError(f"{what} must be contiguous")
 
 
+def _check_out(t: torch.Tensor, numel: int, dtype, device, what: str) -> None:
+    """Output tensors receive raw device writes of numel values: their size,
+    dtype and device are checked here (the C ABI cannot see them)."""
+    _check_device_tensor(t, what)
+    if t.numel() != numel or t.dtype != dtype or t.device != device:
+        raise ValueError(f"{what} needs {numel} values of {dtype} on {device}")
+
+
+def _out_list(out, count: int, n: int, dtype, device, what: str) -> list:
+    res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=device) for _ in range(count)]
+    if len(res) != count:
+        raise ValueError(f"{what} needs {count} tensors")
+    for j, t in enumerate(res):
+        _check_out(t, n, dtype, device, f"{what}[{j}]")
+    return res
+
+
 def _matrices(a: Batch, structure: str, accuracy: str):
     """Build the eig3_matrices descriptor; returns (descriptor, n, dtype,
     device, layout, keepalive)."""
@@ -102,9 +119,7 @@ def eig3_invariants(a: Batch, structure: str = "general", accuracy: str = "fma",
     """(I1, J2, J3, Delta), each a tensor of n values (Alg. alg:I1-stable,
     alg:J2-stable, alg:J3-stable, alg:disc-stable)."""
     m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
-    outs = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(4)]
-    for t in outs:
-        _check_device_tensor(t, "out")
+    outs = _out_list(out, 4, n, dtype, dev, "out")
     _capi.call_invariants(m, [t.data_ptr() if n else 0 for t in outs], _stream(dev))
     return tuple(outs)
 
@@ -115,14 +130,12 @@ def eig3_eigvals(a: Batch, structure: str = "general", accuracy: str = "fma", ou
     m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
     if out_layout == "aos":
         res = out if out is not None else torch.empty((n, 3), dtype=dtype, device=dev)
-        _check_device_tensor(res, "out")
+        _check_out(res, 3 * n, dtype, dev, "out")
         ptrs = [res.data_ptr() if n else 0, 0, 0]
         _capi.call_eigvals(m, EIG3_AOS, ptrs, _stream(dev))
         return res
     if out_layout == "soa":
-        res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(3)]
-        for t in res:
-            _check_device_tensor(t, "out")
+        res = _out_list(out, 3, n, dtype, dev, "out")
         _capi.call_eigvals(m, EIG3_SOA, [t.data_ptr() if n else 0 for t in res], _stream(dev))
         return tuple(res)
     raise ValueError("out_layout must be 'aos' or 'soa'")
@@ -134,27 +147,21 @@ def eig3_eigvals_backward(a: Batch, g: Batch, structure: str = "general", accura
     m, n, dtype, dev, layout, _keep = _matrices(a, structure, accuracy)
     k = 9 if structure == "general" else 6
     if isinstance(g, torch.Tensor):
-        _check_device_tensor(g, "g")
-        if g.numel() != 3 * n or g.dtype != dtype:
-            raise ValueError("g needs 3 values per matrix and the dtype of a")
+        _check_out(g, 3 * n, dtype, dev, "g")
         g_layout, gp, gkeep = EIG3_AOS, [g.data_ptr() if n else 0, 0, 0], [g]
     else:
         gkeep = list(g)
         if len(gkeep) != 3:
             raise ValueError("g needs three tensors")
-        for t in gkeep:
-            _check_device_tensor(t, "g")
-            if t.numel() != n or t.dtype != dtype:
-                raise ValueError("each g tensor needs n values and the dtype of a")
+        for j, t in enumerate(gkeep):
+            _check_out(t, n, dtype, dev, f"g[{j}]")
         g_layout, gp = EIG3_SOA, [t.data_ptr() if n else 0 for t in gkeep]
     if layout == EIG3_AOS:
         res = out if out is not None else torch.empty_like(a)
-        _check_device_tensor(res, "out")
+        _check_out(res, k * n, dtype, dev, "out")
         ptrs = [res.data_ptr() if n else 0] + [0] * 8
     else:
-        res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(k)]
-        for t in res:
-            _check_device_tensor(t, "out")
+        res = _out_list(out, k, n, dtype, dev, "out")
         ptrs = [t.data_ptr() if n else 0 for t in res] + [0] * (9 - k)
     _capi.call_eigvals_backward(m, g_layout, gp, ptrs, _stream(dev))
     return res if layout == EIG3_AOS else tuple(res)
@@ -169,17 +176,15 @@ def eig3_mohr_coulomb(sigma: Batch, s_yc: float, m: float, structure: str = "sym
     k = 9 if structure == "general" else 6
     f, dfds = (out if out is not None else (None, None))
     f = f if f is not None else torch.empty(n, dtype=dtype, device=dev)
-    _check_device_tensor(f, "f")
+    _check_out(f, n, dtype, dev, "f")
     ptrs = None
     if grad:
         if layout == EIG3_AOS:
             dfds = dfds if dfds is not None else torch.empty_like(sigma)
-            _check_device_tensor(dfds, "dfds")
+            _check_out(dfds, k * n, dtype, dev, "dfds")
             ptrs = [dfds.data_ptr() if n else 0] + [0] * 8
         else:
-            dfds = list(dfds) if dfds is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(k)]
-            for t in dfds:
-                _check_device_tensor(t, "dfds")
+            dfds = _out_list(dfds, k, n, dtype, dev, "dfds")
             ptrs = [t.data_ptr() if n else 0 for t in dfds] + [0] * (9 - k)
             dfds = tuple(dfds)
     else:
@@ -197,13 +202,11 @@ def eig3_eigenprojectors(a: Batch, structure: str = "general", accuracy: str = "
     k = 9 if structure == "general" else 6
     if out_layout == "aos":
         res = out if out is not None else torch.empty((n, 3, k), dtype=dtype, device=dev)
-        _check_device_tensor(res, "out")
+        _check_out(res, 3 * k * n, dtype, dev, "out")
         _capi.call_eigenprojectors(m, EIG3_AOS, [res.data_ptr() if n else 0] + [0] * 26, _stream(dev))
         return res
     if out_layout == "soa":
-        res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=dev) for _ in range(3 * k)]
-        for t in res:
-            _check_device_tensor(t, "out")
+        res = _out_list(out, 3 * k, n, dtype, dev, "out")
         _capi.call_eigenprojectors(m, EIG3_SOA, [t.data_ptr() if n else 0 for t in res] + [0] * (27 - 3 * k),
                                    _stream(dev))
         return tuple(res)

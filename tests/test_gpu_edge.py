@@ -127,3 +127,32 @@ def test_scaling_range(eig3, scale):
     inv = download_inv(eig3.eig3_invariants(upload(a, "soa")))
     check(inv_errors(t, inv), t.bound_inv(), what=f"invariants scale {scale}")
     assert math.isfinite(float(np.abs(inv).max()))
+
+
+def test_output_tensors_validated(eig3):
+    """Caller-supplied outputs of the wrong size, dtype or count are rejected
+    by the binding before anything is launched."""
+    import torch
+    d = torch.device("cuda:0")
+    f64 = torch.float64
+    a = torch.zeros((100, 9), dtype=f64, device=d)
+    s = torch.zeros((100, 6), dtype=f64, device=d)
+    g = torch.zeros((100, 3), dtype=f64, device=d)
+    bad = [
+        lambda: eig3.eig3_eigvals(a, out=torch.empty((99, 3), dtype=f64, device=d)),
+        lambda: eig3.eig3_eigvals(a, out=torch.empty((100, 3), dtype=torch.float32, device=d)),
+        lambda: eig3.eig3_eigvals(a, out_layout="soa", out=[torch.empty(100, dtype=f64, device=d)] * 2),
+        lambda: eig3.eig3_invariants(a, out=[torch.empty(100, dtype=f64, device=d) for _ in range(3)]),
+        lambda: eig3.eig3_invariants(a, out=[torch.empty(n, dtype=f64, device=d) for n in (100, 100, 100, 50)]),
+        lambda: eig3.eig3_eigvals_backward(a, g, out=torch.empty((100, 8), dtype=f64, device=d)),
+        lambda: eig3.eig3_eigvals_backward(a, g[:50]),
+        lambda: eig3.eig3_eigenprojectors(a, out=torch.empty((100, 3, 6), dtype=f64, device=d)),
+        lambda: eig3.eig3_mohr_coulomb(s, 100.0, 10.0, out=(torch.empty(99, dtype=f64, device=d), None)),
+        lambda: eig3.eig3_mohr_coulomb(s, 100.0, 10.0, out=(None, torch.empty((100, 9), dtype=f64, device=d))),
+    ]
+    for j, call in enumerate(bad):
+        with pytest.raises(ValueError):
+            call()
+    # well-formed outputs still work
+    lam = eig3.eig3_eigvals(a, out=torch.empty((100, 3), dtype=f64, device=d))
+    assert torch.all(lam == 0)
