@@ -243,16 +243,18 @@ __device__ __forceinline__ Inv invariants_symmetric_fma(const Sym &S)
     const double d0 = g.d0, d1 = g.d1, d2 = g.d2;
     const double a = S.s01, b = S.s02, c = S.s12;
     const double ab = a * b, ac = a * c, bc = b * c;
-    const double u2 = fma_(-ab, d2, (q01 - q02) * c);
+    // the three differences of squares, each also used negated
+    const double q01m02 = q01 - q02, q01m12 = q01 - q12, q02m12 = q02 - q12;
+    const double u2 = fma_(-ab, d2, q01m02 * c);
     const double u3 = fma_(ac, d1, fma_(-q01, b, q12 * b));
     const double u4 = fma_(bc, d0, fma_(-q02, a, q12 * a));
     const double d0d1 = d0 * d1, d1d2 = d1 * d2, d0d2 = d0 * d2;
-    const double u8 = fma_(c, d0d1, fma_(-ab, d1, (q01 - q12) * c));
-    const double u9 = fma_(c, d0d1, fma_(-ab, d0, (q02 - q12) * c));
-    const double u10 = fma_(a, d1d2, fma_(bc, d2, (q02 - q01) * a));
-    const double u11 = fma_(a, d1d2, fma_(bc, d1, (q12 - q01) * a));
-    const double u12 = fma_(-b, d0d2, fma_(ac, d0, (q12 - q02) * b));
-    const double u13 = fma_(b, d0d2, fma_(ac, d2, (q02 - q01) * b));
+    const double u8 = fma_(c, d0d1, fma_(-ab, d1, q01m12 * c));
+    const double u9 = fma_(c, d0d1, fma_(-ab, d0, q02m12 * c));
+    const double u10 = fma_(a, d1d2, fma_(bc, d2, -q01m02 * a));
+    const double u11 = fma_(a, d1d2, fma_(bc, d1, -q01m12 * a));
+    const double u12 = fma_(-b, d0d2, fma_(ac, d0, -q02m12 * b));
+    const double u13 = fma_(b, d0d2, fma_(ac, d2, -q01m02 * b));
     const double u14 = fma_(d0d1, d2, fma_(-q01, d0, fma_(q02, d1, -q12 * d2)));
     // the squares grouped by weight; every partial sum is nonnegative
     double s2 = u13 * u13;
@@ -851,7 +853,10 @@ __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float
     // root (1 ulp) serves.
     // A zero member takes no part in the choice (its frexp exponent, 0, would
     // otherwise outvote a tiny partner and leave it subnormal in binary32).
-    const double d = 27.0 * clamp0(v.disc);
+    // (NaN in J2 or Delta comes only from NaN or Inf entries, which make J3
+    // NaN too; the J3 test below carries it to the output, so plain max
+    // clamps suffice here)
+    const double d = 27.0 * fmax(v.disc, 0.0);
     const double x = 27.0 * fabs(v.j3);
     constexpr int kNone = -4096;
     const int ex = x > 0.0 ? __builtin_amdgcn_frexp_exp(x) : kNone;
@@ -864,7 +869,7 @@ __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float
     float s, c;
     sincos_sixth<false>(psi * (1.0f / 3.0f), s, c);
     // r = sqrt(J2 / 3) the same way: q 2^-2k in [1/4, 1), r = sqrt(that) 2^k
-    const double q = clamp0(v.j2) * kThird;
+    const double q = fmax(v.j2, 0.0) * kThird;
     const int k = (__builtin_amdgcn_frexp_exp(q) + 1) >> 1;
     const float r = ldexpf(__builtin_amdgcn_sqrtf(float(ldexp(q, -2 * k))), k);
     const float mean = float(v.i1 * kThird);
