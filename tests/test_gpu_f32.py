@@ -148,3 +148,30 @@ def test_f32_special_matrices(eig3, acc):
     t = Truth(g[:9].astype(np.float64), np.ones(9))
     check(lam_errors(t, lam[:9]), t.bound_lam(EPS32), what=f"f32 special matrices {acc}")
     assert np.isnan(lam[9:]).all()
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_general_invariants_f32(eig3, c1f, acc):
+    """General binary32 invariants (nonsymmetric storage path) against the
+    exact invariants of the binary32 input; J3 and Delta where binary32
+    normal, as for the symmetric batch."""
+    a32, t = c1f
+    inv = download_inv(eig3.eig3_invariants(upload(a32, "soa"), "general", acc))
+    err = inv_errors(t, inv)
+    normal = np.abs(t.inv) >= F32_TINY
+    normal[:, :2] = True
+    check(np.where(normal, err, 0.0), t.bound_inv(EPS32), what=f"general f32 invariants {acc}")
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_eigenprojectors_f32(eig3, layout):
+    """binary32 eigenprojectors: binary64 arithmetic on the widened entries,
+    rounded once; against the exact Frobenius covariants of the binary32
+    input (well-separated spectra, kappa <= 100)."""
+    c = w.config5(256, seed=85)
+    a32 = c["a"].astype(np.float32)
+    e = eig3.eig3_eigenprojectors(upload(a32, layout), "general", "fma", "aos").double().cpu().numpy()
+    e = e.reshape(-1, 27)
+    for m in range(0, 256, 4):
+        ref = np.array(exact.eigenprojectors(a32[m].astype(np.float64)))
+        assert np.abs(e[m] - ref).max() <= 4 * EPS32 * np.abs(ref).max(), m
