@@ -18,6 +18,9 @@ def pytest_configure(config):
     from oracle import build as oracle_build
     if not os.path.exists(oracle_build.LIB):
         oracle_build.build()
+    from c_abi import build as c_build
+    if not os.path.exists(c_build.EXE):
+        c_build.build()
 
 
 @pytest.fixture(scope="session")
