@@ -275,70 +275,160 @@ __device__ __forceinline__ Inv invariants_symmetric_fma(const Sym &S)
 // pair products and TwoSum, so that each r_i, J2 and J3 carries the accuracy
 // of twice the working precision before its final rounding.
 
+// The operands of dx(M; d0, d1, d2) with every pair product formed once,
+// exactly, as hi + lo.
+template <class T> struct DxPairs {
+    T M01, M02, M10, M12, M20, M21, d0, d1, d2;
+    PairT<T> d0d1, d1d2, d0d2;
+    PairT<T> m01m12, m02m10, m01m02, m01m01, m02m02, m01m21, m02m21, m02m12, m01m10, m12m12, m02m20, m12m21;
+};
+
+template <class T>
+__device__ __forceinline__ DxPairs<T> dx_pairs(T M01, T M02, T M10, T M12, T M20, T M21, T d0, T d1, T d2,
+                                               const PairT<T> &d0d1, const PairT<T> &d1d2, const PairT<T> &d0d2)
+{
+    DxPairs<T> p{M01, M02, M10, M12, M20, M21, d0, d1, d2, d0d1, d1d2, d0d2, {}, {}, {}, {}, {}, {}, {}, {}, {}, {},
+                 {}, {}};
+    p.m01m12 = pair(M01, M12);
+    p.m02m10 = pair(M02, M10);
+    p.m01m02 = pair(M01, M02);
+    p.m01m01 = pair(M01, M01);
+    p.m02m02 = pair(M02, M02);
+    p.m01m21 = pair(M01, M21);
+    p.m02m21 = pair(M02, M21);
+    p.m02m12 = pair(M02, M12);
+    p.m01m10 = pair(M01, M10);
+    p.m12m12 = pair(M12, M12);
+    p.m02m20 = pair(M02, M20);
+    p.m12m21 = pair(M12, M21);
+    return p;
+}
+
+// r_(I+1) of dx, compensated, returned as hi + lo.
+template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPairs<T> &p, T &hi, T &lo)
+{
+    AccT<T> a;
+    if constexpr (I == 0) {
+        a.first(p.m01m12, p.M20);
+        a.add(neg(p.m02m10), p.M21);
+    } else if constexpr (I == 1) {
+        a.first(neg(p.m01m02), p.d2);
+        a.add(p.m01m01, p.M12);
+        a.add(neg(p.m02m02), p.M21);
+    } else if constexpr (I == 2) {
+        a.first(p.m01m21, p.d1);
+        a.add(neg(p.m01m01), p.M20);
+        a.add(p.m02m21, p.M21);
+    } else if constexpr (I == 3) {
+        a.first(p.m02m12, p.d0);
+        a.add(p.m01m12, p.M12);
+        a.add(neg(p.m02m02), p.M10);
+    } else if constexpr (I == 4) {
+        a.first(p.m01m12, p.d1);
+        a.add(neg(p.m01m02), p.M10);
+        a.add(p.m02m12, p.M21);
+    } else if constexpr (I == 5) {
+        a.first(p.m02m21, p.d0);
+        a.add(neg(p.m01m02), p.M20);
+        a.add(p.m01m12, p.M21);
+    } else if constexpr (I == 6) {
+        a.first(neg(p.m02m10), p.d2);
+        a.add(p.m01m10, p.M12);
+        a.add(neg(p.m02m12), p.M20);
+    } else if constexpr (I == 7) {
+        a.first(p.d0d1, p.M12);
+        a.add(neg(p.m02m10), p.d1);
+        a.add(p.m01m10, p.M12);
+        a.add(neg(p.m12m12), p.M21);
+    } else if constexpr (I == 8) {
+        a.first(p.d0d1, p.M12);
+        a.add(neg(p.m02m10), p.d0);
+        a.add(p.m02m12, p.M20);
+        a.add(neg(p.m12m12), p.M21);
+    } else if constexpr (I == 9) {
+        a.first(p.d1d2, p.M01);
+        a.add(p.m02m21, p.d2);
+        a.add(p.m01m02, p.M20);
+        a.add(neg(p.m01m01), p.M10);
+    } else if constexpr (I == 10) {
+        a.first(p.d1d2, p.M01);
+        a.add(p.m02m21, p.d1);
+        a.add(p.m01m12, p.M21);
+        a.add(neg(p.m01m01), p.M10);
+    } else if constexpr (I == 11) {
+        a.first(neg(p.d0d2), p.M02);
+        a.add(p.m01m12, p.d0);
+        a.add(p.m02m12, p.M21);
+        a.add(neg(p.m02m02), p.M20);
+    } else if constexpr (I == 12) {
+        a.first(p.d0d2, p.M02);
+        a.add(p.m01m12, p.d2);
+        a.add(neg(p.m01m02), p.M10);
+        a.add(p.m02m02, p.M20);
+    } else {
+        a.first(p.d0d1, p.d2);
+        a.add(neg(p.m01m10), p.d0);
+        a.add(p.m02m20, p.d1);
+        a.add(neg(p.m12m21), p.d2);
+    }
+    a.split(hi, lo);
+}
+
+template <int I, class T> __device__ __forceinline__ void dx_comp_all(const DxPairs<T> &p, T rh[14], T rl[14])
+{
+    dx_comp_r<I>(p, rh[I], rl[I]);
+    if constexpr (I < 13)
+        dx_comp_all<I + 1>(p, rh, rl);
+}
+
+// all fourteen r_i of dx, compensated
 template <class T>
 __device__ __forceinline__ void dx_comp(T M01, T M02, T M10, T M12, T M20, T M21, T d0, T d1, T d2,
                                         const PairT<T> &d0d1, const PairT<T> &d1d2, const PairT<T> &d0d2,
                                         T rh[14], T rl[14])
 {
-    const PairT<T> m01m12 = pair(M01, M12), m02m10 = pair(M02, M10), m01m02 = pair(M01, M02);
-    const PairT<T> m01m01 = pair(M01, M01), m02m02 = pair(M02, M02), m01m21 = pair(M01, M21);
-    const PairT<T> m02m21 = pair(M02, M21), m02m12 = pair(M02, M12), m01m10 = pair(M01, M10);
-    const PairT<T> m12m12 = pair(M12, M12), m02m20 = pair(M02, M20), m12m21 = pair(M12, M21);
-    AccT<T> a;
-#define EIG3_R(i, expr)          \
-    {                            \
-        expr;                    \
-        a.split(rh[i], rl[i]);   \
-    }
-    EIG3_R(0, a.first(m01m12, M20); a.add(neg(m02m10), M21))
-    EIG3_R(1, a.first(neg(m01m02), d2); a.add(m01m01, M12); a.add(neg(m02m02), M21))
-    EIG3_R(2, a.first(m01m21, d1); a.add(neg(m01m01), M20); a.add(m02m21, M21))
-    EIG3_R(3, a.first(m02m12, d0); a.add(m01m12, M12); a.add(neg(m02m02), M10))
-    EIG3_R(4, a.first(m01m12, d1); a.add(neg(m01m02), M10); a.add(m02m12, M21))
-    EIG3_R(5, a.first(m02m21, d0); a.add(neg(m01m02), M20); a.add(m01m12, M21))
-    EIG3_R(6, a.first(neg(m02m10), d2); a.add(m01m10, M12); a.add(neg(m02m12), M20))
-    EIG3_R(7, a.first(d0d1, M12); a.add(neg(m02m10), d1); a.add(m01m10, M12); a.add(neg(m12m12), M21))
-    EIG3_R(8, a.first(d0d1, M12); a.add(neg(m02m10), d0); a.add(m02m12, M20); a.add(neg(m12m12), M21))
-    EIG3_R(9, a.first(d1d2, M01); a.add(m02m21, d2); a.add(m01m02, M20); a.add(neg(m01m01), M10))
-    EIG3_R(10, a.first(d1d2, M01); a.add(m02m21, d1); a.add(m01m12, M21); a.add(neg(m01m01), M10))
-    EIG3_R(11, a.first(neg(d0d2), M02); a.add(m01m12, d0); a.add(m02m12, M21); a.add(neg(m02m02), M20))
-    EIG3_R(12, a.first(d0d2, M02); a.add(m01m12, d2); a.add(neg(m01m02), M10); a.add(m02m02, M20))
-    EIG3_R(13, a.first(d0d1, d2); a.add(neg(m01m10), d0); a.add(m02m20, d1); a.add(neg(m12m21), d2))
-#undef EIG3_R
+    dx_comp_all<0>(dx_pairs(M01, M02, M10, M12, M20, M21, d0, d1, d2, d0d1, d1d2, d0d2), rh, rl);
 }
 
-// sum_i w_i u_i v_i with u, v given as hi + lo; weights scale exactly except
-// 6 and 9, which are applied as exact pair products.
-__device__ __forceinline__ double sum_wuv_comp(const double uh[14], const double ul[14], const double vh[14],
-                                               const double vl[14])
+// sum_i w_i u_i v_i, u = dx(A) and v = dx(A^T) as hi + lo, compensated;
+// weights scale exactly except 6 and 9, which are applied as exact pair
+// products.  u_i and v_i are formed index by index and consumed at once
+// rather than all fourteen of each first (fewer values live).
+template <int I>
+__device__ __forceinline__ void sum_wuv_comp_step(const DxPairs<double> &pu, const DxPairs<double> &pv, double &s,
+                                                  double &c)
 {
-    const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
-    double s, c;
-    {
-        double p, pe;
-        two_prod(uh[0], vh[0], p, pe);
-        s = w[0] * p;
-        c = w[0] * fma_(uh[0], vl[0], fma_(ul[0], vh[0], pe));
-        // w[0] * p is exact up to one rounding; keep its error
-        c = c + fma_(w[0], p, -s);
-    }
-#pragma unroll
-    for (int i = 1; i < 14; ++i) {
-        double p, pe, t, te;
-        two_prod(uh[i], vh[i], p, pe);
-        const double corr = fma_(uh[i], vl[i], fma_(ul[i], vh[i], pe));
-        if (w[i] == 8.0 || w[i] == 2.0 || w[i] == 1.0) {
-            // a power of two scales exactly
-            two_sum(s, w[i] * p, t, te);
-            c = c + fma_(w[i], corr, te);
-        } else {
-            double wp, wpe;
-            two_prod(w[i], p, wp, wpe);
-            two_sum(s, wp, t, te);
-            c = c + (te + fma_(w[i], corr, wpe));
-        }
+    constexpr double w = kW[I];
+    double uh, ul, vh, vl, p, pe;
+    dx_comp_r<I>(pu, uh, ul);
+    dx_comp_r<I>(pv, vh, vl);
+    two_prod(uh, vh, p, pe);
+    const double corr = fma_(uh, vl, fma_(ul, vh, pe));
+    if constexpr (I == 0) {
+        s = w * p;
+        // w * p is exact up to one rounding; keep its error
+        c = w * corr + fma_(w, p, -s);
+    } else if constexpr (w == 8.0 || w == 2.0 || w == 1.0) {
+        // a power of two scales exactly
+        double t, te;
+        two_sum(s, w * p, t, te);
+        c = c + fma_(w, corr, te);
+        s = t;
+    } else {
+        double wp, wpe, t, te;
+        two_prod(w, p, wp, wpe);
+        two_sum(s, wp, t, te);
+        c = c + (te + fma_(w, corr, wpe));
         s = t;
     }
+    if constexpr (I < 13)
+        sum_wuv_comp_step<I + 1>(pu, pv, s, c);
+}
+
+__device__ __forceinline__ double sum_wuv_comp(const DxPairs<double> &pu, const DxPairs<double> &pv)
+{
+    double s = 0.0, c = 0.0;
+    sum_wuv_comp_step<0>(pu, pv, s, c);
     return s + c;
 }
 
@@ -375,10 +465,9 @@ __device__ __forceinline__ Inv invariants_general_comp(const Gen &A)
     // Delta
     {
         const Pair d0d1 = pair(g.d0, g.d1), d1d2 = pair(g.d1, g.d2), d0d2 = pair(g.d0, g.d2);
-        double uh[14], ul[14], vh[14], vl[14];
-        dx_comp(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, uh, ul);
-        dx_comp(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, vh, vl);
-        r.disc = sum_wuv_comp(uh, ul, vh, vl);
+        r.disc = sum_wuv_comp(
+            dx_pairs(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2),
+            dx_pairs(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2));
     }
     return r;
 }
