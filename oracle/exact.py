@@ -246,24 +246,48 @@ def eigvals_vjp(a9: Sequence[float], g: Sequence[float], dps: int = 80) -> list[
         return [float(grad[r][c]) for r in range(3) for c in range(3)]
 
 
-def eigenprojectors(a9: Sequence[float], dps: int = 80) -> list[float]:
-    """E_1, E_2, E_3 (ascending eigenvalues), 27 floats, each row-major:
-    the Frobenius covariants E_k = prod_{j != k} (A - lambda_j I) /
+def _eigenprojectors_mp(a9: Sequence[float], dps: int):
+    """(lambda_1..3 ascending, [E_1, E_2, E_3] as 3x3 mpmath matrices): the
+    Frobenius covariants E_k = prod_{j != k} (A - lambda_j I) /
     (lambda_k - lambda_j) of a real, distinct spectrum (the projectors of the
-    relation E_k^T = d(lambda_k)/dA in Sec. "Introduction and motivation")."""
+    relation E_k^T = d(lambda_k)/dA in Sec. "Introduction and motivation").
+    Evaluate inside ``mpmath.workdps(dps)``."""
     lam = eigvals(a9, dps)
     if any(isinstance(x, mpmath.mpc) for x in lam):
         raise ValueError("complex spectrum")
+    a = [[mpmath.mpf(float(a9[3 * i + j])) for j in range(3)] for i in range(3)]
+    es = []
+    for k in range(3):
+        i, j = [m for m in range(3) if m != k]
+        p = [[a[r][c] - (lam[i] if r == c else 0) for c in range(3)] for r in range(3)]
+        q = [[a[r][c] - (lam[j] if r == c else 0) for c in range(3)] for r in range(3)]
+        den = (lam[k] - lam[i]) * (lam[k] - lam[j])
+        es.append([[sum(p[r][t] * q[t][c] for t in range(3)) / den for c in range(3)] for r in range(3)])
+    return lam, es
+
+
+def eigenprojectors(a9: Sequence[float], dps: int = 80) -> list[float]:
+    """E_1, E_2, E_3 (ascending eigenvalues), 27 floats, each row-major."""
     with mpmath.workdps(dps):
-        a = [[mpmath.mpf(float(a9[3 * i + j])) for j in range(3)] for i in range(3)]
-        out = []
-        for k in range(3):
-            i, j = [m for m in range(3) if m != k]
-            p = [[a[r][c] - (lam[i] if r == c else 0) for c in range(3)] for r in range(3)]
-            q = [[a[r][c] - (lam[j] if r == c else 0) for c in range(3)] for r in range(3)]
-            den = (lam[k] - lam[i]) * (lam[k] - lam[j])
-            out += [float(sum(p[r][t] * q[t][c] for t in range(3)) / den) for r in range(3) for c in range(3)]
-        return out
+        _, es = _eigenprojectors_mp(a9, dps)
+        return [float(e[r][c]) for e in es for r in range(3) for c in range(3)]
+
+
+MATRIX_FUNCTIONS = {"exp": mpmath.exp, "log": mpmath.log, "sqrt": mpmath.sqrt}
+
+
+def matrix_function(a9: Sequence[float], fn: str, dps: int = 80) -> list[float]:
+    """f(A) = sum_k f(lambda_k) E_k, row-major, for f in MATRIX_FUNCTIONS: the
+    functions of matrices that closed-form eigenprojectors give (Sec.
+    "Introduction and motivation"), for a real, distinct spectrum (log and
+    sqrt: positive eigenvalues)."""
+    f = MATRIX_FUNCTIONS[fn]
+    with mpmath.workdps(dps):
+        lam, es = _eigenprojectors_mp(a9, dps)
+        if fn != "exp" and min(lam) <= 0:
+            raise ValueError(f"{fn} needs positive eigenvalues")
+        fl = [f(x) for x in lam]
+        return [float(sum(fl[k] * es[k][r][c] for k in range(3))) for r in range(3) for c in range(3)]
 
 
 # ----------------------------------------------------------------------------

@@ -285,3 +285,55 @@ def test_eigenprojector_identities():
         vi = c["vinv"][m].reshape(3, 3)
         for k in range(3):
             np.testing.assert_allclose(e[k], np.outer(v[:, k], vi[k, :]), atol=1e-9 * np.abs(e[k]).max())
+
+
+def _spd(rng, lo=0.3, hi=3.0):
+    """Symmetric positive definite: Q diag(l) Q^T with Haar Q, l ~ U[lo, hi]."""
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    lam = np.sort(rng.uniform(lo, hi, 3))
+    return (q @ np.diag(lam) @ q.T).ravel()
+
+
+def test_matrix_functions_against_scipy():
+    """exp against scipy.linalg.expm (Pade scaling and squaring) on general
+    matrices; log and sqrt against scipy.linalg.logm / sqrtm (Schur based) on
+    symmetric positive definite ones: independent algorithms."""
+    import scipy.linalg as sl
+    import workloads as w
+    c = w.config5(6, seed=11)
+    for m in range(6):
+        a = c["a"][m]
+        e = np.array(exact.matrix_function(a, "exp")).reshape(3, 3)
+        ref = sl.expm(a.reshape(3, 3))
+        assert np.abs(e - ref).max() <= 1e-12 * np.abs(ref).max()
+    rng = np.random.default_rng(12)
+    for _ in range(6):
+        a = _spd(rng)
+        for fn, ref in (("log", sl.logm(a.reshape(3, 3))), ("sqrt", sl.sqrtm(a.reshape(3, 3)))):
+            got = np.array(exact.matrix_function(a, fn)).reshape(3, 3)
+            assert np.abs(got - np.real(ref)).max() <= 1e-12 * np.abs(ref).max(), fn
+
+
+def test_matrix_functions_closed_forms_and_identities():
+    """f(diag(d)) = diag(f(d)); f of a similarity transform is the similarity
+    transform of f on the diagonal (exactly invertible integer basis);
+    sqrt(A)^2 = A and exp(log A) = A."""
+    d = [0.5, 2.0, 7.0]
+    a = np.diag(d).ravel()
+    for fn, f in (("exp", np.exp), ("log", np.log), ("sqrt", np.sqrt)):
+        assert np.allclose(np.array(exact.matrix_function(a, fn)).reshape(3, 3), np.diag(f(d)), rtol=1e-15, atol=0)
+    p = np.array([[1, 1, 0], [0, 1, 1], [0, 0, 1]], dtype=float)   # unimodular
+    pinv = np.array([[1, -1, 1], [0, 1, -1], [0, 0, 1]], dtype=float)
+    b = (p @ np.diag(d) @ pinv).ravel()
+    got = np.array(exact.matrix_function(b, "exp")).reshape(3, 3)
+    ref = p @ np.diag(np.exp(d)) @ pinv
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    rng = np.random.default_rng(13)
+    a = _spd(rng)
+    s = np.array(exact.matrix_function(a, "sqrt")).reshape(3, 3)
+    assert np.abs(s @ s - a.reshape(3, 3)).max() <= 1e-14 * np.abs(a).max()
+    lg = np.array(exact.matrix_function(a, "log"))
+    assert np.abs(np.array(exact.matrix_function(lg, "exp")) - a).max() <= 1e-13 * np.abs(a).max()
+    with pytest.raises(ValueError):
+        exact.matrix_function(np.diag([-1.0, 1.0, 2.0]).ravel(), "log")
