@@ -41,6 +41,7 @@ BYTES = {
     "step_general_f32": (9 * 4 + 3 * 4) + (9 * 4 + 3 * 4 + 9 * 4),
     "mohr_coulomb_symmetric_f64": 6 * 8 + 8 + 6 * 8,
     "eigenprojectors_general_f64": 9 * 8 + 27 * 8,
+    "matrix_function_general_f64": 9 * 8 + 9 * 8,
 }
 
 
@@ -301,6 +302,11 @@ def main():
         variant("config5 eigenprojectors general f64 fma", "eigenprojectors_general_f64", N_MAIN,
                 lambda: eig3.eig3_eigenprojectors(a, "general", "fma", "soa", out=eproj), "f64")
         del eproj
+        # a function of each matrix through the eigenprojectors (9 outputs)
+        fexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
+        variant("config5 matrix exponential general f64 fma", "matrix_function_general_f64", N_MAIN,
+                lambda: eig3.eig3_matrix_function(a, "exp", "general", "fma", out=fexp), "f64")
+        del fexp
         # the same batch as one (n, 3, 3) array of structures (LDS-staged loads)
         a_aos = torch.stack(a, dim=1).contiguous()
         lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)

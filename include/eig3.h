@@ -188,6 +188,29 @@ int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f
  */
 int eig3_eigenprojectors(const eig3_matrices *A, int32_t out_layout, void *const E[27], hipStream_t stream);
 
+typedef enum eig3_function {
+    EIG3_EXP = 0,  /* matrix exponential */
+    EIG3_LOG = 1,  /* principal logarithm: needs positive eigenvalues */
+    EIG3_SQRT = 2  /* principal square root: needs nonnegative eigenvalues */
+} eig3_function;
+
+/*
+ * A function of each matrix, f(A) = sum_k f(lambda_k) E_k with the closed-form
+ * eigenprojectors above (the use of closed-form eigenprojectors that
+ * Sec. "Introduction and motivation" names, e.g. the matrix exponential).
+ * Through the invariants this is the transpose of the vector-Jacobian product
+ * of eig3_eigvals_backward with g_k = f(lambda_k):
+ *   f(A) = (f1 + f2 + f3)/3 I + (sum_k f_k mu_k / G_k) S + (sum_k f_k / G_k) dev(cof S)^T.
+ * out: the structure and layout of A (GENERAL: 9 entries; SYMMETRIC: the 6
+ * components of the symmetric result), element type of A; arithmetic in
+ * binary64.  fn: an eig3_function.  Needs distinct eigenvalues (as for the
+ * eigenprojectors, the error grows like 1/gap and exactly repeated
+ * eigenvalues give NaN); eigenvalues outside the domain of f (log, sqrt)
+ * give NaN.  accuracy: FMA or COMPENSATED (the comparators return
+ * EIG3_EUNSUPPORTED).
+ */
+int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9], hipStream_t stream);
+
 /* Static, human-readable name of a status code. */
 const char *eig3_status_string(int status);
 

@@ -24,7 +24,8 @@ from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EI
                     EIG3_NAIVE_TENSOR, EIG3_SOA, EIG3_SYMMETRIC, Eig3Error)
 
 __all__ = [
-    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors", "eigvals",
+    "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors",
+    "eig3_matrix_function", "eigvals",
     "Eig3Eigvals",
     "ENTRIES", "Eig3Error", "version",
 ]
@@ -37,6 +38,7 @@ ENTRIES = {
 _STRUCT = {"general": EIG3_GENERAL, "symmetric": EIG3_SYMMETRIC}
 _ACC = {"fma": EIG3_FMA, "compensated": EIG3_COMPENSATED, "naive": EIG3_NAIVE, "naive_tensor": EIG3_NAIVE_TENSOR}
 _DTYPE = {torch.float64: EIG3_F64, torch.float32: EIG3_F32}
+_FN = {"exp": 0, "log": 1, "sqrt": 2}  # eig3_function
 
 Batch = Union[torch.Tensor, Sequence[torch.Tensor]]
 
@@ -211,6 +213,24 @@ def eig3_eigenprojectors(a: Batch, structure: str = "general", accuracy: str = "
                                    _stream(dev))
         return tuple(res)
     raise ValueError("out_layout must be 'aos' or 'soa'")
+
+
+def eig3_matrix_function(a: Batch, fn: str = "exp", structure: str = "general", accuracy: str = "fma", out=None):
+    """f(A) = sum_k f(lambda_k) E_k for fn in ('exp', 'log', 'sqrt'), in the
+    structure and layout of ``a`` (symmetric: the 6 components)."""
+    if fn not in _FN:
+        raise ValueError(f"fn must be one of {tuple(_FN)}")
+    m, n, dtype, dev, layout, _keep = _matrices(a, structure, accuracy)
+    k = 9 if structure == "general" else 6
+    if layout == EIG3_AOS:
+        res = out if out is not None else torch.empty_like(a)
+        _check_out(res, k * n, dtype, dev, "out")
+        ptrs = [res.data_ptr() if n else 0] + [0] * 8
+    else:
+        res = _out_list(out, k, n, dtype, dev, "out")
+        ptrs = [t.data_ptr() if n else 0 for t in res] + [0] * (9 - k)
+    _capi.call_matrix_function(m, _FN[fn], ptrs, _stream(dev))
+    return res if layout == EIG3_AOS else tuple(res)
 
 
 class Eig3Eigvals(torch.autograd.Function):

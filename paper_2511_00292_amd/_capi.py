@@ -65,6 +65,8 @@ def lib():
         l.eig3_mohr_coulomb.restype = ctypes.c_int
         l.eig3_eigenprojectors.argtypes = [pm, ctypes.c_int32, ctypes.POINTER(vp), vp]
         l.eig3_eigenprojectors.restype = ctypes.c_int
+        l.eig3_matrix_function.argtypes = [pm, ctypes.c_int32, ctypes.POINTER(vp), vp]
+        l.eig3_matrix_function.restype = ctypes.c_int
         l.eig3_status_string.argtypes = [ctypes.c_int]
         l.eig3_status_string.restype = ctypes.c_char_p
         l.eig3_version.argtypes = []
@@ -114,6 +116,13 @@ def call_mohr_coulomb(m: Eig3Matrices, s_yc: float, mm: float, f: int, grads, st
                                  ctypes.c_void_p(stream))
     if st != EIG3_OK:
         raise Eig3Error(st, "eig3_mohr_coulomb")
+
+
+def call_matrix_function(m: Eig3Matrices, fn: int, outs, stream: int) -> None:
+    arr = (ctypes.c_void_p * 9)(*outs)
+    st = lib().eig3_matrix_function(ctypes.byref(m), fn, arr, ctypes.c_void_p(stream))
+    if st != EIG3_OK:
+        raise Eig3Error(st, "eig3_matrix_function")
 
 
 def call_eigenprojectors(m: Eig3Matrices, out_layout: int, outs, stream: int) -> None:

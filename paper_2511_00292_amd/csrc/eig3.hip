@@ -550,6 +550,22 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
     });
 }
 
+// A function of each matrix (exp, log, sqrt) through the eigenprojectors;
+// binary64 arithmetic for either storage type; the result in the structure
+// and layout of A (symmetric: the 6 components).
+template <class T, int S, int L, int Acc, int Fn>
+EIG3_KERNEL void k_matrix_function(int64_t n, In9<T> in, OutK<T, Mat<T, S>::K> out)
+{
+    constexpr int KO = Mat<T, S>::K;
+    for_each_matrix<T, S, L, KO, L>(n, in, out, [&](const Span &, const Mat<T, S> &mt, double (&o)[KO]) {
+        const Mat<double, S> m = widen(mt);
+        const Inv v = invariants_of<S, Acc>(m);
+        double F[9];
+        matrix_function_general<Fn>(general_of(m), v, F);
+        gradient_rows<S, kTensor>(F, o);
+    });
+}
+
 // ------------------------------------------------------------------- host
 // one workgroup per span of kBlock matrices, up to kMaxBlocks (the grid
 // strides beyond that)
@@ -720,6 +736,49 @@ const char *eig3_status_string(int status)
     default:
         return "unknown eig3 status";
     }
+}
+
+int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9], hipStream_t stream)
+{
+    int st = check_matrices(A);
+    if (st != EIG3_OK)
+        return st;
+    if (out == nullptr || !valid_enum(fn, 2))
+        return EIG3_EINVAL;
+    if (A->n == 0)
+        return EIG3_OK;
+    if (comparator(A->accuracy))
+        return EIG3_EUNSUPPORTED;
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    const int nout = A->layout == EIG3_SOA ? K : 1;
+    void *outs[9];
+    for (int k = 0; k < nout; ++k)
+        outs[k] = out[k];
+    if ((st = check_outputs(A, outs, nout, size_t(A->n) * (nout == 1 ? K : 1))) != EIG3_OK)
+        return st;
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    auto launch = [&](auto tag) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(A);
+        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            constexpr int KO = S.value == EIG3_GENERAL ? 9 : 6;
+            const OutK<T, KO> o = out_slots<T, KO>(outs, nout);
+            if (fn == EIG3_EXP)
+                hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_EXP>), grid, block, 0,
+                                   stream, A->n, in, o);
+            else if (fn == EIG3_LOG)
+                hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_LOG>), grid, block, 0,
+                                   stream, A->n, in, o);
+            else
+                hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_SQRT>), grid, block, 0,
+                                   stream, A->n, in, o);
+        });
+    };
+    if (A->dtype == EIG3_F32)
+        launch(float{});
+    else
+        launch(double{});
+    return launched();
 }
 
 const char *eig3_version(void) { return "0.1.0"; }

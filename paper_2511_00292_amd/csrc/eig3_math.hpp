@@ -1045,6 +1045,35 @@ __device__ __forceinline__ void backward_general(const Gen &A, const Coef &k, do
     grad[8] = fma_(k.a, s22, fma_(k.b, c22, k.gsum3));
 }
 
+// ============================================================ functions of A
+// f(A) = sum_k f(lambda_k) E_k, E_k = I/3 + (mu_k S + dev(cof S)^T) / G_k:
+// the transpose of the adjoint above with g_k = f(lambda_k).
+template <int Fn> __device__ __forceinline__ double scalar_function(double x)
+{
+    if constexpr (Fn == EIG3_EXP)
+        return exp(x);
+    else if constexpr (Fn == EIG3_LOG)
+        return log(x);
+    else
+        return sqrt(x);
+}
+
+template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Inv &v, double F[9])
+{
+    const Trig t = trig_from_invariants<false>(v);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    const Coef c = backward_coefficients(t, scalar_function<Fn>(t.mean + m1), scalar_function<Fn>(t.mean + m2),
+                                         scalar_function<Fn>(t.mean + m3));
+    double g[9];
+    backward_general(A, c, g);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            F[3 * r + k] = g[3 * k + r];
+}
+
 // ============================================================ Mohr-Coulomb
 // Yield function of the paper's application section:
 //   f(sigma) = (1/S_yc) ((m + 1)/2) max_{i<j} (|s_i - s_j| + K (s_i + s_j)) - 1,

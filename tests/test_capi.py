@@ -130,3 +130,17 @@ def test_eigenprojector_outputs_all_checked(lib):
                                  ctypes.c_void_p(f), grads, None) == capi.EIG3_EINVAL
     assert lib.eig3_mohr_coulomb(ctypes.byref(m), ctypes.c_double(0.0), ctypes.c_double(10.0),
                                  ctypes.c_void_p(f), None, None) == capi.EIG3_EINVAL
+
+
+def test_matrix_function_arguments(lib):
+    n = 1024
+    base = 0x20000000
+    ins = [base + j * n * 8 for j in range(9)]
+    m = _mat(n=n, ptrs=ins)
+    outs = (ctypes.c_void_p * 9)(*[0x40000000 + j * 0x100000 for j in range(9)])
+    assert lib.eig3_matrix_function(ctypes.byref(m), 3, outs, None) == capi.EIG3_EINVAL      # unknown function
+    assert lib.eig3_matrix_function(ctypes.byref(m), -1, outs, None) == capi.EIG3_EINVAL
+    alias = (ctypes.c_void_p * 9)(*([0x40000000 + j * 0x100000 for j in range(8)] + [ins[2]]))
+    assert lib.eig3_matrix_function(ctypes.byref(m), 0, alias, None) == capi.EIG3_EINVAL     # output aliases input
+    m0 = _mat(n=0, ptrs=[0] * 9)
+    assert lib.eig3_matrix_function(ctypes.byref(m0), 0, (ctypes.c_void_p * 9)(*([0] * 9)), None) == capi.EIG3_OK

@@ -1,0 +1,96 @@
+"""Functions of matrices (eig3_matrix_function): f(A) = sum_k f(lambda_k) E_k
+with the closed-form eigenprojectors, against the exact oracle (80-digit
+eigenprojectors and f), on general matrices with separated spectra and on
+symmetric positive definite ones; identities and the domain rule."""
+import numpy as np
+import pytest
+
+import workloads as w
+from accuracy import EPS32
+from gpu_util import download_matrix, upload
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eig3():
+    import paper_2511_00292_amd as m
+    return m
+
+
+def _spd(n, seed, lo=0.3, hi=3.0, gap=1e-2):
+    """Q diag(l) Q^T, Haar Q, l ~ U[lo, hi] sorted with gaps >= gap."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        lam = np.sort(rng.uniform(lo, hi, 3))
+        if np.diff(lam).min() >= gap:
+            out.append((q @ np.diag(lam) @ q.T).ravel())
+    return np.array(out)
+
+
+def _rel(got, ref):
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+@pytest.mark.parametrize("acc", ["fma", "compensated"])
+def test_exp_general(eig3, layout, acc):
+    """exp on the differentiation batch (kappa <= 100, gaps >= 1e-3)."""
+    c = w.config5(1000, seed=91)
+    res = download_matrix(eig3.eig3_matrix_function(upload(c["a"], layout), "exp", "general", acc), 9)
+    for m in range(0, 1000, 8):
+        assert _rel(res[m], np.array(exact.matrix_function(c["a"][m], "exp"))) <= 1e-12, m
+
+
+@pytest.mark.parametrize("fn", ["exp", "log", "sqrt"])
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_symmetric_positive_definite(eig3, fn, layout):
+    """exp, log, sqrt of SPD matrices in symmetric storage (6 components)."""
+    a = _spd(600, 92)
+    s = np.stack([a[:, 0], a[:, 4], a[:, 8], a[:, 1], a[:, 2], a[:, 5]], axis=1)
+    res = download_matrix(eig3.eig3_matrix_function(upload(s, layout), fn, "symmetric"), 6)
+    for m in range(0, 600, 6):
+        ref = np.array(exact.matrix_function(a[m], fn)).reshape(3, 3)
+        ref6 = np.array([ref[0, 0], ref[1, 1], ref[2, 2], ref[0, 1], ref[0, 2], ref[1, 2]])
+        assert _rel(res[m], ref6) <= 1e-13, (fn, m)
+
+
+def test_identities_and_domain(eig3):
+    """exp(log A) = A and sqrt(A)^2 = A for SPD A (2^16 matrices); the log of a
+    matrix with a negative eigenvalue is NaN."""
+    import torch
+    a = _spd(1 << 16, 93)
+    ad = upload(a, "aos")
+    lg = eig3.eig3_matrix_function(ad, "log")
+    back = eig3.eig3_matrix_function(lg, "exp").cpu().numpy()
+    scale = np.abs(a).max(1)
+    assert np.all(np.abs(back - a).max(1) <= 1e-13 * scale)
+    r = eig3.eig3_matrix_function(ad, "sqrt").reshape(-1, 3, 3)
+    sq = torch.matmul(r, r).reshape(-1, 9).cpu().numpy()
+    assert np.all(np.abs(sq - a).max(1) <= 1e-13 * scale)
+    neg = np.diag([-1.0, 1.0, 2.0]).ravel()[None, :].repeat(4, axis=0)
+    out = eig3.eig3_matrix_function(upload(neg, "aos"), "log").cpu().numpy()
+    assert np.isnan(out).any(axis=1).all()
+
+
+def test_binary32_storage(eig3):
+    """binary32 storage: binary64 arithmetic on the widened entries, rounded
+    once; against the exact f of the binary32 input."""
+    c = w.config5(512, seed=94)
+    a32 = c["a"].astype(np.float32)
+    res = download_matrix(eig3.eig3_matrix_function(upload(a32, "aos"), "exp"), 9)
+    for m in range(0, 512, 8):
+        ref = np.array(exact.matrix_function(a32[m].astype(np.float64), "exp"))
+        assert _rel(res[m], ref) <= 4 * EPS32, m
+
+
+def test_rejects(eig3):
+    c = w.config1(16, seed=95)
+    with pytest.raises(ValueError):
+        eig3.eig3_matrix_function(upload(c["a"], "aos"), "sin")
+    with pytest.raises(eig3.Eig3Error):
+        eig3.eig3_matrix_function(upload(c["a"], "aos"), "exp", "general", "naive")
