@@ -56,6 +56,11 @@ int main(void) {
     expect(eig3_mohr_coulomb(&m, -1.0, 10.0, P(0x7F000000), NULL, NULL), EIG3_EINVAL, "bad s_yc");
     expect(eig3_invariants(&m, P(0x50000000), P(0x51000000), P(0x52000000), (void *)m.a[8], NULL), EIG3_EINVAL,
            "invariants alias input");
+    void *fo[9];
+    for (int j = 0; j < 9; ++j) fo[j] = P(0x78000000 + j * 0x100000);
+    expect(eig3_matrix_function(&m, 7, fo, NULL), EIG3_EINVAL, "unknown matrix function");
+    fo[4] = (void *)m.a[0];
+    expect(eig3_matrix_function(&m, EIG3_EXP, fo, NULL), EIG3_EINVAL, "matrix function aliases input");
     m.n = -5;
     expect(eig3_eigvals(&m, EIG3_SOA, lam, NULL), EIG3_EINVAL, "n < 0");
     m.n = 0;
