@@ -290,6 +290,38 @@ def matrix_function(a9: Sequence[float], fn: str, dps: int = 80) -> list[float]:
         return [float(sum(fl[k] * es[k][r][c] for k in range(3))) for r in range(3) for c in range(3)]
 
 
+MATRIX_FUNCTION_DERIVATIVES = {"exp": mpmath.exp, "log": lambda x: 1 / x, "sqrt": lambda x: 1 / (2 * mpmath.sqrt(x))}
+
+
+def matrix_function_vjp(a9: Sequence[float], fn: str, g9: Sequence[float], dps: int = 80) -> list[float]:
+    """d<G, f(A)>/dA, row-major: with f(A) = sum_k f(lambda_k) E_k, the
+    derivative of a function of a matrix with distinct eigenvalues is
+    d f(A) = sum_{k,l} Gamma_kl E_k dA E_l (Daleckii-Krein), Gamma_kk =
+    f'(lambda_k), Gamma_kl = (f(lambda_k) - f(lambda_l)) / (lambda_k - lambda_l),
+    so the vector-Jacobian product is sum_{k,l} Gamma_kl E_k^T G E_l^T."""
+    f, df = MATRIX_FUNCTIONS[fn], MATRIX_FUNCTION_DERIVATIVES[fn]
+    with mpmath.workdps(dps):
+        lam, es = _eigenprojectors_mp(a9, dps)
+        if fn != "exp" and min(lam) <= 0:
+            raise ValueError(f"{fn} needs positive eigenvalues")
+        g = [[mpmath.mpf(float(g9[3 * i + j])) for j in range(3)] for i in range(3)]
+        gam = [[df(lam[k]) if k == l else (f(lam[k]) - f(lam[l])) / (lam[k] - lam[l]) for l in range(3)]
+               for k in range(3)]
+
+        def mm(x, y):
+            return [[sum(x[r][t] * y[t][c] for t in range(3)) for c in range(3)] for r in range(3)]
+
+        def tr(x):
+            return [[x[c][r] for c in range(3)] for r in range(3)]
+
+        out = [[mpmath.mpf(0)] * 3 for _ in range(3)]
+        for k in range(3):
+            for l in range(3):
+                t = mm(mm(tr(es[k]), g), tr(es[l]))
+                out = [[out[r][c] + gam[k][l] * t[r][c] for c in range(3)] for r in range(3)]
+        return [float(out[r][c]) for r in range(3) for c in range(3)]
+
+
 # ----------------------------------------------------------------------------
 # stability-bound scales (C = 1, Frobenius norms, lowest-order term)
 # ----------------------------------------------------------------------------
