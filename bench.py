@@ -42,6 +42,7 @@ BYTES = {
     "mohr_coulomb_symmetric_f64": 6 * 8 + 8 + 6 * 8,
     "eigenprojectors_general_f64": 9 * 8 + 27 * 8,
     "matrix_function_general_f64": 9 * 8 + 9 * 8,
+    "matrix_function_backward_general_f64": 9 * 8 + 9 * 8 + 9 * 8,
 }
 
 
@@ -306,7 +307,10 @@ def main():
         fexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
         variant("config5 matrix exponential general f64 fma", "matrix_function_general_f64", N_MAIN,
                 lambda: eig3.eig3_matrix_function(a, "exp", "general", "fma", out=fexp), "f64")
-        del fexp
+        gexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
+        variant("config5 matrix exponential adjoint general f64 fma", "matrix_function_backward_general_f64", N_MAIN,
+                lambda: eig3.eig3_matrix_function_backward(a, fexp, "exp", "general", "fma", out=gexp), "f64")
+        del fexp, gexp
         # the same batch as one (n, 3, 3) array of structures (LDS-staged loads)
         a_aos = torch.stack(a, dim=1).contiguous()
         lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)

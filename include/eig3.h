@@ -211,6 +211,24 @@ typedef enum eig3_function {
  */
 int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9], hipStream_t stream);
 
+/*
+ * Vector-Jacobian product of eig3_matrix_function: grad_a = d<G, f(A)>/dA.
+ * The derivative of a function of a matrix with distinct eigenvalues follows
+ * from the same eigenprojectors (Sec. "Introduction and motivation": closed
+ * forms for functions of matrices and their derivatives):
+ *   d f(A) = sum_{k,l} Gamma_kl E_k dA E_l,  grad_a = sum_{k,l} Gamma_kl E_k^T G E_l^T,
+ * Gamma_kk = f'(lambda_k), Gamma_kl = (f(lambda_k) - f(lambda_l)) / (lambda_k - lambda_l),
+ * the divided differences formed from the eigenvalue gaps without
+ * cancellation (exp: e^y expm1(d)/d, log: log1p(d/y)/d, sqrt: 1/(sqrt x + sqrt y)).
+ * g: the upstream gradient in the structure and layout of the forward's
+ * output (GENERAL: 9 entries; SYMMETRIC: dL/d of the 6 stored components).
+ * grad_a: the structure and layout of A (SYMMETRIC: the derivative with
+ * respect to each stored entry).  Arithmetic in binary64.  Needs distinct
+ * eigenvalues; outside the domain of f the result is NaN.
+ */
+int eig3_matrix_function_backward(const eig3_matrices *A, int32_t fn, const void *const g[9], void *const grad_a[9],
+                                  hipStream_t stream);
+
 /* Static, human-readable name of a status code. */
 const char *eig3_status_string(int status);
 

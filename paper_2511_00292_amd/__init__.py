@@ -25,8 +25,8 @@ from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EI
 
 __all__ = [
     "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors",
-    "eig3_matrix_function", "eigvals",
-    "Eig3Eigvals",
+    "eig3_matrix_function", "eig3_matrix_function_backward", "eigvals", "matrix_function",
+    "Eig3Eigvals", "Eig3MatrixFunction",
     "ENTRIES", "Eig3Error", "version",
 ]
 
@@ -231,6 +231,63 @@ def eig3_matrix_function(a: Batch, fn: str = "exp", structure: str = "general", 
         ptrs = [t.data_ptr() if n else 0 for t in res] + [0] * (9 - k)
     _capi.call_matrix_function(m, _FN[fn], ptrs, _stream(dev))
     return res if layout == EIG3_AOS else tuple(res)
+
+
+def eig3_matrix_function_backward(a: Batch, g: Batch, fn: str = "exp", structure: str = "general",
+                                  accuracy: str = "fma", out=None):
+    """d<G, f(A)>/dA in the structure and layout of ``a``; ``g`` in the
+    layout of the forward's output (that of ``a``)."""
+    if fn not in _FN:
+        raise ValueError(f"fn must be one of {tuple(_FN)}")
+    m, n, dtype, dev, layout, _keep = _matrices(a, structure, accuracy)
+    k = 9 if structure == "general" else 6
+    if layout == EIG3_AOS:
+        if not isinstance(g, torch.Tensor):
+            raise ValueError("g must have the layout of a (one tensor)")
+        _check_out(g, k * n, dtype, dev, "g")
+        gp, gkeep = [g.data_ptr() if n else 0] + [0] * 8, [g]
+        res = out if out is not None else torch.empty_like(a)
+        _check_out(res, k * n, dtype, dev, "out")
+        ptrs = [res.data_ptr() if n else 0] + [0] * 8
+    else:
+        gkeep = list(g) if not isinstance(g, torch.Tensor) else None
+        if gkeep is None or len(gkeep) != k:
+            raise ValueError(f"g must have the layout of a ({k} tensors)")
+        for j, t in enumerate(gkeep):
+            _check_out(t, n, dtype, dev, f"g[{j}]")
+        gp = [t.data_ptr() if n else 0 for t in gkeep] + [0] * (9 - k)
+        res = _out_list(out, k, n, dtype, dev, "out")
+        ptrs = [t.data_ptr() if n else 0 for t in res] + [0] * (9 - k)
+    _capi.call_matrix_function_backward(m, _FN[fn], gp, ptrs, _stream(dev))
+    return res if layout == EIG3_AOS else tuple(res)
+
+
+class Eig3MatrixFunction(torch.autograd.Function):
+    """F = f(A) for A of shape (..., 3, 3) (general, distinct eigenvalues),
+    f in ('exp', 'log', 'sqrt'), with eig3_matrix_function_backward as its
+    backward."""
+
+    @staticmethod
+    def forward(ctx, a: torch.Tensor, fn: str = "exp", accuracy: str = "fma"):
+        if a.shape[-2:] != (3, 3):
+            raise ValueError("expected (..., 3, 3)")
+        ac = a.contiguous()
+        f = eig3_matrix_function(ac.reshape(-1, 9), fn, "general", accuracy)
+        ctx.save_for_backward(ac)
+        ctx.fn, ctx.accuracy = fn, accuracy
+        return f.reshape(ac.shape)
+
+    @staticmethod
+    def backward(ctx, gf: torch.Tensor):
+        (ac,) = ctx.saved_tensors
+        grad = eig3_matrix_function_backward(ac.reshape(-1, 9), gf.contiguous().reshape(-1, 9), ctx.fn, "general",
+                                             ctx.accuracy)
+        return grad.reshape(ac.shape), None, None
+
+
+def matrix_function(a: torch.Tensor, fn: str = "exp", accuracy: str = "fma") -> torch.Tensor:
+    """f(A) of a (..., 3, 3) device tensor, differentiable."""
+    return Eig3MatrixFunction.apply(a, fn, accuracy)
 
 
 class Eig3Eigvals(torch.autograd.Function):

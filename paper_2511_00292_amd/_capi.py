@@ -67,6 +67,8 @@ def lib():
         l.eig3_eigenprojectors.restype = ctypes.c_int
         l.eig3_matrix_function.argtypes = [pm, ctypes.c_int32, ctypes.POINTER(vp), vp]
         l.eig3_matrix_function.restype = ctypes.c_int
+        l.eig3_matrix_function_backward.argtypes = [pm, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        l.eig3_matrix_function_backward.restype = ctypes.c_int
         l.eig3_status_string.argtypes = [ctypes.c_int]
         l.eig3_status_string.restype = ctypes.c_char_p
         l.eig3_version.argtypes = []
@@ -123,6 +125,14 @@ def call_matrix_function(m: Eig3Matrices, fn: int, outs, stream: int) -> None:
     st = lib().eig3_matrix_function(ctypes.byref(m), fn, arr, ctypes.c_void_p(stream))
     if st != EIG3_OK:
         raise Eig3Error(st, "eig3_matrix_function")
+
+
+def call_matrix_function_backward(m: Eig3Matrices, fn: int, g, outs, stream: int) -> None:
+    garr = (ctypes.c_void_p * 9)(*g)
+    arr = (ctypes.c_void_p * 9)(*outs)
+    st = lib().eig3_matrix_function_backward(ctypes.byref(m), fn, garr, arr, ctypes.c_void_p(stream))
+    if st != EIG3_OK:
+        raise Eig3Error(st, "eig3_matrix_function_backward")
 
 
 def call_eigenprojectors(m: Eig3Matrices, out_layout: int, outs, stream: int) -> None:

@@ -566,6 +566,39 @@ EIG3_KERNEL void k_matrix_function(int64_t n, In9<T> in, OutK<T, Mat<T, S>::K> o
     });
 }
 
+// Vector-Jacobian product of the matrix function: g in the layout of A
+// (the forward's output), the gradient in the structure and layout of A.
+template <class T, int S, int L, int Acc, int Fn>
+EIG3_KERNEL void k_matrix_function_backward(int64_t n, In9<T> in, In9<T> gin, OutK<T, Mat<T, S>::K> out)
+{
+    constexpr int KO = Mat<T, S>::K;
+    for_each_matrix<T, S, L, KO, L>(n, in, out, [&](const Span &sp, const Mat<T, S> &mt, double (&o)[KO]) {
+        const Mat<double, S> m = widen(mt);
+        const Inv v = invariants_of<S, Acc>(m);
+        double gk[KO];
+#pragma unroll
+        for (int k = 0; k < KO; ++k)
+            gk[k] = double(L == EIG3_SOA ? span_ld(gin.p[k], sp) : span_ld(gin.p[0], sp, KO, k));
+        double G[9];
+        if constexpr (S == EIG3_GENERAL) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                G[k] = gk[k];
+        } else {
+            // dL/dF for the symmetric F from dL/d(its 6 stored components)
+            G[0] = gk[0];
+            G[4] = gk[1];
+            G[8] = gk[2];
+            G[1] = G[3] = 0.5 * gk[3];
+            G[2] = G[6] = 0.5 * gk[4];
+            G[5] = G[7] = 0.5 * gk[5];
+        }
+        double gr[9];
+        matrix_function_backward_general<Fn>(general_of(m), v, G, gr);
+        gradient_rows<S, kStored>(gr, o);
+    });
+}
+
 // ------------------------------------------------------------------- host
 // one workgroup per span of kBlock matrices, up to kMaxBlocks (the grid
 // strides beyond that)
@@ -772,6 +805,64 @@ int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9],
             else
                 hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_SQRT>), grid, block, 0,
                                    stream, A->n, in, o);
+        });
+    };
+    if (A->dtype == EIG3_F32)
+        launch(float{});
+    else
+        launch(double{});
+    return launched();
+}
+
+int eig3_matrix_function_backward(const eig3_matrices *A, int32_t fn, const void *const g[9], void *const grad_a[9],
+                                  hipStream_t stream)
+{
+    int st = check_matrices(A);
+    if (st != EIG3_OK)
+        return st;
+    if (g == nullptr || grad_a == nullptr || !valid_enum(fn, 2))
+        return EIG3_EINVAL;
+    if (A->n == 0)
+        return EIG3_OK;
+    if (comparator(A->accuracy))
+        return EIG3_EUNSUPPORTED;
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    const size_t es = elem_size(A->dtype);
+    const int np = A->layout == EIG3_SOA ? K : 1;
+    const size_t each = size_t(A->n) * (np == 1 ? K : 1);
+    for (int k = 0; k < np; ++k)
+        if (g[k] == nullptr || !aligned(g[k], es))
+            return EIG3_EINVAL;
+    void *outs[9];
+    for (int k = 0; k < np; ++k)
+        outs[k] = grad_a[k];
+    if ((st = check_outputs(A, outs, np, each)) != EIG3_OK)
+        return st;
+    for (int j = 0; j < np; ++j) {
+        const Range o{uintptr_t(outs[j]), uintptr_t(outs[j]) + each * es};
+        for (int k = 0; k < np; ++k)
+            if (overlaps(o, Range{uintptr_t(g[k]), uintptr_t(g[k]) + each * es}))
+                return EIG3_EINVAL;
+    }
+    const dim3 grid(unsigned(grid_for(A->n))), block(kBlock);
+    auto launch = [&](auto tag) {
+        using T = decltype(tag);
+        const In9<T> in = inputs_of<T>(A);
+        In9<T> gin;
+        for (int k = 0; k < 9; ++k)
+            gin.p[k] = k < np ? static_cast<const T *>(g[k]) : nullptr;
+        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
+            constexpr int KO = S.value == EIG3_GENERAL ? 9 : 6;
+            const OutK<T, KO> o = out_slots<T, KO>(outs, np);
+            if (fn == EIG3_EXP)
+                hipLaunchKernelGGL((k_matrix_function_backward<T, S.value, L.value, Acc.value, EIG3_EXP>), grid,
+                                   block, 0, stream, A->n, in, gin, o);
+            else if (fn == EIG3_LOG)
+                hipLaunchKernelGGL((k_matrix_function_backward<T, S.value, L.value, Acc.value, EIG3_LOG>), grid,
+                                   block, 0, stream, A->n, in, gin, o);
+            else
+                hipLaunchKernelGGL((k_matrix_function_backward<T, S.value, L.value, Acc.value, EIG3_SQRT>), grid,
+                                   block, 0, stream, A->n, in, gin, o);
         });
     };
     if (A->dtype == EIG3_F32)

@@ -686,6 +686,20 @@ __device__ __forceinline__ void mu_from_trig(const Trig &t, double &m1, double &
     m3 = t.neg ? -a1 : a3;
 }
 
+// The eigenvalue gaps mu2 - mu1, mu3 - mu1, mu3 - mu2 (all >= 0) from the
+// trigonometric form, free of cancellation (for the |J3| configuration, with
+// the roles of the two outer gaps swapped when J3 < 0).
+struct Gaps {
+    double e12, e13, e23;
+};
+__device__ __forceinline__ Gaps gaps_from_trig(const Trig &t)
+{
+    const double e13 = t.r * fma_(3.0, t.c, kSqrt3 * t.s);
+    const double e23p = t.r * fma_(3.0, t.c, -kSqrt3 * t.s);
+    const double e12p = 2.0 * kSqrt3 * t.r * t.s;
+    return Gaps{t.neg ? e23p : e12p, e13, t.neg ? e12p : e23p};
+}
+
 __device__ __forceinline__ void eigvals_from_invariants(const Inv &v, double &l1, double &l2, double &l3)
 {
     const Trig t = trig_from_invariants(v);
@@ -988,12 +1002,8 @@ __device__ __forceinline__ Coef backward_coefficients(const Trig &t, double g1, 
 {
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
-    // gaps of the |J3| configuration; for J3 < 0 they swap roles
-    const double e13 = t.r * fma_(3.0, t.c, kSqrt3 * t.s);
-    const double e23p = t.r * fma_(3.0, t.c, -kSqrt3 * t.s);
-    const double e12p = 2.0 * kSqrt3 * t.r * t.s;
-    const double e12 = t.neg ? e23p : e12p; // mu2 - mu1
-    const double e23 = t.neg ? e12p : e23p; // mu3 - mu2
+    const Gaps gp = gaps_from_trig(t);
+    const double e12 = gp.e12, e13 = gp.e13, e23 = gp.e23;
     const double G1 = e12 * e13;   // (mu1 - mu2)(mu1 - mu3)
     const double G2 = -e12 * e23;  // (mu2 - mu1)(mu2 - mu3)
     const double G3 = e13 * e23;   // (mu3 - mu1)(mu3 - mu2)
@@ -1045,35 +1055,6 @@ __device__ __forceinline__ void backward_general(const Gen &A, const Coef &k, do
     grad[8] = fma_(k.a, s22, fma_(k.b, c22, k.gsum3));
 }
 
-// ============================================================ functions of A
-// f(A) = sum_k f(lambda_k) E_k, E_k = I/3 + (mu_k S + dev(cof S)^T) / G_k:
-// the transpose of the adjoint above with g_k = f(lambda_k).
-template <int Fn> __device__ __forceinline__ double scalar_function(double x)
-{
-    if constexpr (Fn == EIG3_EXP)
-        return exp(x);
-    else if constexpr (Fn == EIG3_LOG)
-        return log(x);
-    else
-        return sqrt(x);
-}
-
-template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Inv &v, double F[9])
-{
-    const Trig t = trig_from_invariants<false>(v);
-    double m1, m2, m3;
-    mu_from_trig(t, m1, m2, m3);
-    const Coef c = backward_coefficients(t, scalar_function<Fn>(t.mean + m1), scalar_function<Fn>(t.mean + m2),
-                                         scalar_function<Fn>(t.mean + m3));
-    double g[9];
-    backward_general(A, c, g);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            F[3 * r + k] = g[3 * k + r];
-}
-
 // ============================================================ Mohr-Coulomb
 // Yield function of the paper's application section:
 //   f(sigma) = (1/S_yc) ((m + 1)/2) max_{i<j} (|s_i - s_j| + K (s_i + s_j)) - 1,
@@ -1118,11 +1099,8 @@ __device__ __forceinline__ void eigenprojectors_general(const Gen &A, const Trig
 {
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
-    const double e13 = t.r * fma_(3.0, t.c, kSqrt3 * t.s);
-    const double e23p = t.r * fma_(3.0, t.c, -kSqrt3 * t.s);
-    const double e12p = 2.0 * kSqrt3 * t.r * t.s;
-    const double e12 = t.neg ? e23p : e12p;
-    const double e23 = t.neg ? e12p : e23p;
+    const Gaps gp = gaps_from_trig(t);
+    const double e12 = gp.e12, e13 = gp.e13, e23 = gp.e23;
     const double inv[3] = {1.0 / (e12 * e13), -1.0 / (e12 * e23), 1.0 / (e13 * e23)};
     const double mu[3] = {m1, m2, m3};
     const Diag g = diag_part(A.a00, A.a11, A.a22);
@@ -1144,6 +1122,97 @@ __device__ __forceinline__ void eigenprojectors_general(const Gen &A, const Trig
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 E[9 * k + 3 * r + c] = fma_(a, S[3 * r + c], fma_(b, C[3 * c + r], r == c ? kThird : 0.0));
+    }
+}
+
+// ============================================================ functions of A
+// f(A) = sum_k f(lambda_k) E_k, E_k = I/3 + (mu_k S + dev(cof S)^T) / G_k:
+// the transpose of the adjoint above with g_k = f(lambda_k).
+template <int Fn> __device__ __forceinline__ double scalar_function(double x)
+{
+    if constexpr (Fn == EIG3_EXP)
+        return exp(x);
+    else if constexpr (Fn == EIG3_LOG)
+        return log(x);
+    else
+        return sqrt(x);
+}
+
+template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Inv &v, double F[9])
+{
+    const Trig t = trig_from_invariants<false>(v);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    const Coef c = backward_coefficients(t, scalar_function<Fn>(t.mean + m1), scalar_function<Fn>(t.mean + m2),
+                                         scalar_function<Fn>(t.mean + m3));
+    double g[9];
+    backward_general(A, c, g);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            F[3 * r + k] = g[3 * k + r];
+}
+
+// Divided difference f[x, y] = (f(x) - f(y)) / (x - y) from y, f(y) and the
+// gap d = x - y >= 0 (computed without cancellation), f'(y) at d = 0.
+template <int Fn> __device__ __forceinline__ double divided_difference(double y, double fx, double fy, double d)
+{
+    if constexpr (Fn == EIG3_EXP)
+        return d == 0.0 ? fy : fy * (expm1(d) / d);
+    else if constexpr (Fn == EIG3_LOG)
+        return d == 0.0 ? 1.0 / y : log1p(d / y) / d;
+    else
+        return 1.0 / (fx + fy);
+}
+
+// The vector-Jacobian product of f(A): with d f(A) = sum_{k,l} Gamma_kl E_k dA
+// E_l (Daleckii-Krein; Gamma_kk = f'(lambda_k), Gamma_kl the divided
+// differences), grad = sum_{k,l} Gamma_kl E_k^T G E_l^T.  G and grad are 3x3
+// row-major.
+template <int Fn>
+__device__ __forceinline__ void matrix_function_backward_general(const Gen &A, const Inv &v, const double G[9],
+                                                                 double grad[9])
+{
+    const Trig t = trig_from_invariants<false>(v);
+    double E[27];
+    eigenprojectors_general(A, t, E);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    const double lam[3] = {t.mean + m1, t.mean + m2, t.mean + m3};
+    const double f[3] = {scalar_function<Fn>(lam[0]), scalar_function<Fn>(lam[1]), scalar_function<Fn>(lam[2])};
+    const Gaps gp = gaps_from_trig(t);
+    const double g12 = divided_difference<Fn>(lam[0], f[1], f[0], gp.e12);
+    const double g13 = divided_difference<Fn>(lam[0], f[2], f[0], gp.e13);
+    const double g23 = divided_difference<Fn>(lam[1], f[2], f[1], gp.e23);
+    const double gam[9] = {divided_difference<Fn>(lam[0], f[0], f[0], 0.0), g12, g13,
+                           g12, divided_difference<Fn>(lam[1], f[1], f[1], 0.0), g23,
+                           g13, g23, divided_difference<Fn>(lam[2], f[2], f[2], 0.0)};
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+        grad[e] = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        // H = G E_l^T
+        double H[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                H[3 * r + c] = fma_(G[3 * r], E[9 * l + 3 * c],
+                                    fma_(G[3 * r + 1], E[9 * l + 3 * c + 1], G[3 * r + 2] * E[9 * l + 3 * c + 2]));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double w = gam[3 * k + l];
+            // grad += w E_k^T H
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    grad[3 * r + c] = fma_(w, fma_(E[9 * k + r], H[c], fma_(E[9 * k + 3 + r], H[3 + c],
+                                                                            E[9 * k + 6 + r] * H[6 + c])),
+                                           grad[3 * r + c]);
+        }
     }
 }
 

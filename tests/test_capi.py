@@ -144,3 +144,17 @@ def test_matrix_function_arguments(lib):
     assert lib.eig3_matrix_function(ctypes.byref(m), 0, alias, None) == capi.EIG3_EINVAL     # output aliases input
     m0 = _mat(n=0, ptrs=[0] * 9)
     assert lib.eig3_matrix_function(ctypes.byref(m0), 0, (ctypes.c_void_p * 9)(*([0] * 9)), None) == capi.EIG3_OK
+
+
+def test_matrix_function_backward_arguments(lib):
+    n = 1024
+    base = 0x20000000
+    ins = [base + j * n * 8 for j in range(9)]
+    m = _mat(n=n, ptrs=ins)
+    g = (ctypes.c_void_p * 9)(*[0x30000000 + j * 0x100000 for j in range(9)])
+    outs = (ctypes.c_void_p * 9)(*[0x40000000 + j * 0x100000 for j in range(9)])
+    assert lib.eig3_matrix_function_backward(ctypes.byref(m), 5, g, outs, None) == capi.EIG3_EINVAL
+    alias = (ctypes.c_void_p * 9)(*([0x40000000 + j * 0x100000 for j in range(8)] + [0x30000000 + 4 * 0x100000]))
+    assert lib.eig3_matrix_function_backward(ctypes.byref(m), 0, g, alias, None) == capi.EIG3_EINVAL  # grad aliases g
+    gnull = (ctypes.c_void_p * 9)(*([0x30000000] * 8 + [0]))
+    assert lib.eig3_matrix_function_backward(ctypes.byref(m), 0, gnull, outs, None) == capi.EIG3_EINVAL

@@ -94,3 +94,57 @@ def test_rejects(eig3):
         eig3.eig3_matrix_function(upload(c["a"], "aos"), "sin")
     with pytest.raises(eig3.Eig3Error):
         eig3.eig3_matrix_function(upload(c["a"], "aos"), "exp", "general", "naive")
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+@pytest.mark.parametrize("acc", ["fma", "compensated"])
+def test_backward_exp_general(eig3, layout, acc):
+    """d<G, exp(A)>/dA against the exact Daleckii-Krein product (kappa <= 100,
+    gaps >= 1e-3)."""
+    c = w.config5(600, seed=96)
+    g = np.random.default_rng(97).standard_normal((600, 9))
+    res = download_matrix(eig3.eig3_matrix_function_backward(upload(c["a"], layout), upload(g, layout), "exp",
+                                                             "general", acc), 9)
+    for m in range(0, 600, 6):
+        ref = np.array(exact.matrix_function_vjp(c["a"][m], "exp", g[m]))
+        assert _rel(res[m], ref) <= 1e-11, m
+
+
+@pytest.mark.parametrize("fn", ["exp", "log", "sqrt"])
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_backward_symmetric_positive_definite(eig3, fn, layout):
+    """Symmetric storage: g = dL/d(the 6 stored components of f(A)), the result
+    dL/d(the 6 stored entries of A)."""
+    a = _spd(300, 98)
+    s = np.stack([a[:, 0], a[:, 4], a[:, 8], a[:, 1], a[:, 2], a[:, 5]], axis=1)
+    g6 = np.random.default_rng(99).standard_normal((300, 6))
+    res = download_matrix(eig3.eig3_matrix_function_backward(upload(s, layout), upload(g6, layout), fn,
+                                                             "symmetric"), 6)
+    for m in range(0, 300, 5):
+        gf = np.array([[g6[m, 0], g6[m, 3] / 2, g6[m, 4] / 2], [g6[m, 3] / 2, g6[m, 1], g6[m, 5] / 2],
+                       [g6[m, 4] / 2, g6[m, 5] / 2, g6[m, 2]]]).ravel()
+        full = np.array(exact.matrix_function_vjp(a[m], fn, gf)).reshape(3, 3)
+        ref = np.array([full[0, 0], full[1, 1], full[2, 2], full[0, 1] + full[1, 0], full[0, 2] + full[2, 0],
+                        full[1, 2] + full[2, 1]])
+        assert _rel(res[m], ref) <= 1e-13, (fn, m)
+
+
+def test_autograd_against_torch_matrix_exp(eig3):
+    """eig3.matrix_function(A, 'exp') and its backward against
+    torch.linalg.matrix_exp and torch's autograd of it (an independent
+    algorithm) on 4096 matrices of the differentiation batch."""
+    import torch
+    c = w.config5(4096, seed=100)
+    a0 = torch.tensor(c["a"].reshape(-1, 3, 3), dtype=torch.float64, device="cuda:0")
+    wgt = torch.tensor(np.random.default_rng(101).standard_normal((4096, 3, 3)), dtype=torch.float64,
+                       device="cuda:0")
+    a1 = a0.clone().requires_grad_(True)
+    f1 = eig3.matrix_function(a1, "exp")
+    (f1 * wgt).sum().backward()
+    a2 = a0.clone().requires_grad_(True)
+    f2 = torch.linalg.matrix_exp(a2)
+    (f2 * wgt).sum().backward()
+    scale_f = f2.detach().abs().amax(dim=(1, 2))
+    assert torch.all((f1 - f2).detach().abs().amax(dim=(1, 2)) <= 1e-11 * scale_f)
+    scale_g = a2.grad.abs().amax(dim=(1, 2))
+    assert torch.all((a1.grad - a2.grad).abs().amax(dim=(1, 2)) <= 1e-10 * scale_g)
