@@ -191,23 +191,32 @@ int eig3_eigenprojectors(const eig3_matrices *A, int32_t out_layout, void *const
 typedef enum eig3_function {
     EIG3_EXP = 0,  /* matrix exponential */
     EIG3_LOG = 1,  /* principal logarithm: needs positive eigenvalues */
-    EIG3_SQRT = 2  /* principal square root: needs nonnegative eigenvalues */
+    EIG3_SQRT = 2  /* principal square root: needs positive eigenvalues (a zero
+                      eigenvalue computed a rounding error below zero, or a
+                      repeated one, gives NaN) */
 } eig3_function;
 
 /*
  * A function of each matrix, f(A) = sum_k f(lambda_k) E_k with the closed-form
- * eigenprojectors above (the use of closed-form eigenprojectors that
- * Sec. "Introduction and motivation" names, e.g. the matrix exponential).
- * Through the invariants this is the transpose of the vector-Jacobian product
- * of eig3_eigvals_backward with g_k = f(lambda_k):
- *   f(A) = (f1 + f2 + f3)/3 I + (sum_k f_k mu_k / G_k) S + (sum_k f_k / G_k) dev(cof S)^T.
+ * eigenvalues and eigenprojectors above (the use of closed-form
+ * eigenprojectors that Sec. "Introduction and motivation" names, e.g. the
+ * matrix exponential).  The sum is the polynomial that interpolates f at the
+ * three eigenvalues, evaluated at A; it is formed in Newton form,
+ *   f(A) = f(lambda1) I + f[lambda1, lambda2] P1 + f[lambda1, lambda2, lambda3] P1 P2,
+ *   P_k = A - lambda_k I,
+ * with the first divided differences taken from the eigenvalue gaps without
+ * cancellation, so the result stays accurate as eigenvalues coalesce and
+ * exactly repeated eigenvalues are covered (f(p I) = f(p) I), where the
+ * eigenprojectors themselves are not.
  * out: the structure and layout of A (GENERAL: 9 entries; SYMMETRIC: the 6
  * components of the symmetric result), element type of A; arithmetic in
- * binary64.  fn: an eig3_function.  Needs distinct eigenvalues (as for the
- * eigenprojectors, the error grows like 1/gap and exactly repeated
- * eigenvalues give NaN); eigenvalues outside the domain of f (log, sqrt)
- * give NaN.  accuracy: FMA or COMPENSATED (the comparators return
- * EIG3_EUNSUPPORTED).
+ * binary64.  fn: an eig3_function.  Eigenvalues outside the domain of f
+ * (log, sqrt) give NaN.  Where computed eigenvalues coincide exactly the
+ * divided differences take their confluent limits (f', f''/2), so the result
+ * is the Hermite interpolant, f(A) also for a defective A (e.g. p I + N, N
+ * strictly triangular); a defective A whose repeated eigenvalue comes out
+ * split gets it only to the accuracy of the computed eigenvalues.
+ * accuracy: FMA or COMPENSATED (the comparators return EIG3_EUNSUPPORTED).
  */
 int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9], hipStream_t stream);
 

@@ -1138,22 +1138,6 @@ template <int Fn> __device__ __forceinline__ double scalar_function(double x)
         return sqrt(x);
 }
 
-template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Inv &v, double F[9])
-{
-    const Trig t = trig_from_invariants<false>(v);
-    double m1, m2, m3;
-    mu_from_trig(t, m1, m2, m3);
-    const Coef c = backward_coefficients(t, scalar_function<Fn>(t.mean + m1), scalar_function<Fn>(t.mean + m2),
-                                         scalar_function<Fn>(t.mean + m3));
-    double g[9];
-    backward_general(A, c, g);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            F[3 * r + k] = g[3 * k + r];
-}
-
 // Divided difference f[x, y] = (f(x) - f(y)) / (x - y) from y, f(y) and the
 // gap d = x - y >= 0 (computed without cancellation), f'(y) at d = 0.
 template <int Fn> __device__ __forceinline__ double divided_difference(double y, double fx, double fy, double d)
@@ -1165,6 +1149,56 @@ template <int Fn> __device__ __forceinline__ double divided_difference(double y,
     else
         return 1.0 / (fx + fy);
 }
+
+// f''(y) / 2 from y and fy = f(y)
+template <int Fn> __device__ __forceinline__ double half_second_derivative(double y, double fy)
+{
+    if constexpr (Fn == EIG3_EXP)
+        return 0.5 * fy;
+    else if constexpr (Fn == EIG3_LOG)
+        return -0.5 / (y * y);
+    else
+        return -0.125 / (y * fy);
+}
+
+// f(A) = sum_k f(lambda_k) E_k is the polynomial interpolating f at the three
+// eigenvalues, evaluated at A; in Newton form
+//   f(A) = f(lambda1) I + f[lambda1, lambda2] P1 + f[lambda1, lambda2, lambda3] P1 P2,
+//   P_k = A - lambda_k I = S - mu_k I,
+// it stays accurate as eigenvalues coalesce (the E_k themselves diverge like
+// 1/gap): the first divided differences come from the gaps without
+// cancellation, and the rounding error of the second, which grows like
+// 1/(lambda3 - lambda1), multiplies P1 P2, which shrinks like the square of
+// the spread.  With exactly repeated eigenvalues the divided differences take
+// their confluent limits (f', f''/2): the Hermite interpolant, which is f(A)
+// also for a defective A.
+template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Inv &v, double F[9])
+{
+    const Trig t = trig_from_invariants<false>(v);
+    double m1, m2, m3;
+    mu_from_trig(t, m1, m2, m3);
+    const double l1 = t.mean + m1, l2 = t.mean + m2;
+    const Gaps gp = gaps_from_trig(t);
+    const double f1 = scalar_function<Fn>(l1), f2 = scalar_function<Fn>(l2);
+    const double d12 = divided_difference<Fn>(l1, f2, f1, gp.e12);
+    const double d23 = divided_difference<Fn>(l2, scalar_function<Fn>(t.mean + m3), f2, gp.e23);
+    // all three equal: the confluent limit f''(lambda) / 2 (P1 P2 is the square
+    // of the nilpotent part, zero unless A is a single Jordan block)
+    const double d123 = gp.e13 == 0.0 ? half_second_derivative<Fn>(l1, f1) : (d23 - d12) / gp.e13;
+    const Diag g = diag_part(A.a00, A.a11, A.a22);
+    // P1 = S - mu1 I, P2 = S - mu2 I with S = dev A from the differences
+    const double s00 = (g.d0 + g.d1) * kThird, s11 = (g.d2 - g.d0) * kThird, s22 = -(g.d1 + g.d2) * kThird;
+    const double P1[9] = {s00 - m1, A.a01, A.a02, A.a10, s11 - m1, A.a12, A.a20, A.a21, s22 - m1};
+    const double P2[9] = {s00 - m2, A.a01, A.a02, A.a10, s11 - m2, A.a12, A.a20, A.a21, s22 - m2};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double pp = fma_(P1[3 * r], P2[c], fma_(P1[3 * r + 1], P2[3 + c], P1[3 * r + 2] * P2[6 + c]));
+            F[3 * r + c] = fma_(d123, pp, fma_(d12, P1[3 * r + c], r == c ? f1 : 0.0));
+        }
+}
+
 
 // The vector-Jacobian product of f(A): with d f(A) = sum_{k,l} Gamma_kl E_k dA
 // E_l (Daleckii-Krein; Gamma_kk = f'(lambda_k), Gamma_kl the divided

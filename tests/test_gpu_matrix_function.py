@@ -1,7 +1,8 @@
-"""Functions of matrices (eig3_matrix_function): f(A) = sum_k f(lambda_k) E_k
-with the closed-form eigenprojectors, against the exact oracle (80-digit
-eigenprojectors and f), on general matrices with separated spectra and on
-symmetric positive definite ones; identities and the domain rule."""
+"""Functions of matrices (eig3_matrix_function): f(A) = sum_k f(lambda_k) E_k,
+evaluated as the interpolation polynomial in Newton form, against the exact
+oracle (80-digit eigenprojectors and f), on general matrices with separated
+spectra, on symmetric positive definite ones and on nearly isotropic ones;
+repeated eigenvalues; identities and the domain rule."""
 import numpy as np
 import pytest
 
@@ -75,6 +76,63 @@ def test_identities_and_domain(eig3):
     neg = np.diag([-1.0, 1.0, 2.0]).ravel()[None, :].repeat(4, axis=0)
     out = eig3.eig3_matrix_function(upload(neg, "aos"), "log").cpu().numpy()
     assert np.isnan(out).any(axis=1).all()
+
+
+@pytest.mark.parametrize("fn", ["exp", "log", "sqrt"])
+@pytest.mark.parametrize("delta", [1e-3, 1e-7, 1e-12])
+def test_nearly_isotropic(eig3, fn, delta):
+    """p I + delta S (S symmetric Gaussian): eigenvalues that all but coalesce.
+    The eigenprojectors themselves are ill-conditioned here, f(A) is not."""
+    rng = np.random.default_rng(97)
+    p = rng.uniform(0.5, 2.0, 300)
+    s = rng.standard_normal((300, 3, 3))
+    a = (p[:, None, None] * np.eye(3) + delta * (s + s.transpose(0, 2, 1)) / 2).reshape(-1, 9)
+    res = download_matrix(eig3.eig3_matrix_function(upload(a, "soa"), fn), 9)
+    for m in range(0, 300, 5):
+        assert _rel(res[m], np.array(exact.matrix_function(a[m], fn))) <= 1e-13, (fn, delta, m)
+
+
+def test_repeated_eigenvalues(eig3):
+    """Exactly repeated eigenvalues: f(p I) = f(p) I and f of diagonal
+    matrices with a double eigenvalue, in both layouts; log I = 0 exactly."""
+    diag = np.array([[1.0, 1.0, 1.0], [2.5, 2.5, 2.5], [1.0, 1.0, 2.0], [3.0, 0.5, 3.0], [0.25, 4.0, 4.0]])
+    a = np.zeros((len(diag), 9))
+    a[:, [0, 4, 8]] = diag
+    for fn, f in (("exp", np.exp), ("log", np.log), ("sqrt", np.sqrt)):
+        for layout in ("soa", "aos"):
+            res = download_matrix(eig3.eig3_matrix_function(upload(a, layout), fn), 9)
+            ref = np.zeros_like(a)
+            ref[:, [0, 4, 8]] = f(diag)
+            assert np.abs(res - ref).max() <= 4e-15 * np.abs(ref).max(), (fn, layout)
+    lg = download_matrix(eig3.eig3_matrix_function(upload(a[:1], "soa"), "log"), 9)
+    assert np.all(lg == 0.0)
+
+
+_DERIVATIVES = {  # f, f', f''/2 in closed form
+    "exp": (np.exp, np.exp, lambda x: np.exp(x) / 2),
+    "log": (np.log, lambda x: 1 / x, lambda x: -0.5 / x**2),
+    "sqrt": (np.sqrt, lambda x: 0.5 / np.sqrt(x), lambda x: -0.125 / x**1.5),
+}
+
+
+@pytest.mark.parametrize("fn", ["exp", "log", "sqrt"])
+def test_defective_jordan_blocks(eig3, fn):
+    """p I + N with N strictly upper or lower triangular (a single Jordan
+    block when N01 N12 != 0): f(A) = f(p) I + f'(p) N + f''(p)/2 N^2, the
+    confluent (Hermite) limit of the interpolation polynomial."""
+    rng = np.random.default_rng(98)
+    p = rng.uniform(0.5, 3.0, 64)
+    n = np.zeros((64, 3, 3))
+    n[:, 0, 1], n[:, 0, 2], n[:, 1, 2] = rng.uniform(-4, 4, (3, 64))
+    n[32:] = n[32:].transpose(0, 2, 1)
+    f0, f1, f2 = _DERIVATIVES[fn]
+    eye = np.eye(3)
+    a = (p[:, None, None] * eye + n).reshape(-1, 9)
+    ref = (f0(p)[:, None, None] * eye + f1(p)[:, None, None] * n
+           + f2(p)[:, None, None] * np.matmul(n, n)).reshape(-1, 9)
+    res = download_matrix(eig3.eig3_matrix_function(upload(a, "soa"), fn), 9)
+    err = np.abs(res - ref).max(1) / np.abs(ref).max(1)
+    assert err.max() <= 1e-14, (fn, int(err.argmax()), err.max())
 
 
 def test_binary32_storage(eig3):
