@@ -39,6 +39,11 @@ constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 #ifndef EIG3_AOS_DIRECT
 #define EIG3_AOS_DIRECT 0
 #endif
+//  EIG3_F32_PAIRS     1: binary32 structure-of-arrays eigenvalues take two
+//                     adjacent matrices per lane (8-byte loads and stores)
+#ifndef EIG3_F32_PAIRS
+#define EIG3_F32_PAIRS 1
+#endif
 #if EIG3_WAVES_PER_EU > 0
 #define EIG3_KERNEL __global__ __launch_bounds__(kBlock, EIG3_WAVES_PER_EU)
 #else
@@ -421,6 +426,63 @@ EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
     });
 }
 
+// Binary32 structure-of-arrays in and out, two adjacent matrices per lane:
+// a workgroup covers a span of 2 kBlock matrices, lane i owns matrices 2i and
+// 2i + 1 of it and moves both with one 8-byte access per array, so each wave
+// keeps twice the bytes in flight of the one-matrix-per-lane launch.  A
+// ragged last span is done one matrix per lane, as two spans of kBlock.
+// (Only launched when every array is 8-byte aligned.)
+template <int S, int Acc> __device__ __forceinline__ void eigvals_f32(const Mat<float, S> &m, float (&l)[3])
+{
+    eigvals_f32_from_invariants(invariants_of<S, Acc>(m), l[0], l[1], l[2]);
+}
+
+template <int S, int Acc> EIG3_KERNEL void k_eigvals_f32x2(int64_t n, In9<float> in, OutK<float, 3> out)
+{
+    constexpr int K = Mat<float, S>::K;
+    constexpr int kSpan = 2 * kBlock;
+    const int64_t stride = int64_t(gridDim.x) * kSpan;
+    for (int64_t first = int64_t(blockIdx.x) * kSpan; first < n; first += stride) {
+        if (n - first >= kSpan) {
+            const int off = int(threadIdx.x) * 8;
+            Mat<float, S> m0, m1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float *>(in.p[k]) + first, 0, kSpan * int(sizeof(float)), kBufferWord3);
+                // (split as a 64-bit integer: a bit cast of the loaded pair to
+                // a two-lane vector lets the compiler narrow the load to 4 bytes)
+                const uint64_t v = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kBufferAux));
+                m0.a[k] = __builtin_bit_cast(float, uint32_t(v));
+                m1.a[k] = __builtin_bit_cast(float, uint32_t(v >> 32));
+            }
+            float l0[3], l1[3];
+            eigvals_f32<S, Acc>(m0, l0);
+            eigvals_f32<S, Acc>(m1, l1);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                    out.p[e] + first, 0, kSpan * int(sizeof(float)), kBufferWord3);
+                const u32x2 v = {__builtin_bit_cast(unsigned, l0[e]), __builtin_bit_cast(unsigned, l1[e])};
+                __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, kBufferAux);
+            }
+        } else {
+#pragma unroll 1
+            for (int64_t f = first; f < n && f < first + kSpan; f += kBlock) {
+                const Span sp = span_at(f, n);
+                if (!sp.live())
+                    continue;
+                Mat<float, S> m;
+                load_soa<float, S>(in, sp, m);
+                float l[3];
+                eigvals_f32<S, Acc>(m, l);
+                const double o[3] = {l[0], l[1], l[2]};
+                store_rows(out, EIG3_SOA, sp, o);
+            }
+        }
+    }
+}
+
 template <class T, int S> __device__ __forceinline__ Mat<double, S> widen(const Mat<T, S> &mt)
 {
     Mat<double, S> m;
@@ -602,9 +664,9 @@ EIG3_KERNEL void k_matrix_function_backward(int64_t n, In9<T> in, In9<T> gin, Ou
 // ------------------------------------------------------------------- host
 // one workgroup per span of kBlock matrices, up to kMaxBlocks (the grid
 // strides beyond that)
-int64_t grid_for(int64_t n)
+int64_t grid_for(int64_t n, int64_t span = kBlock)
 {
-    const int64_t b = (n + kBlock - 1) / kBlock;
+    const int64_t b = (n + span - 1) / span;
     return b < kMaxBlocks ? b : kMaxBlocks;
 }
 
@@ -636,6 +698,20 @@ int input_ranges(const eig3_matrices *A, Range *r)
 bool overlaps(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi; }
 
 bool aligned(const void *p, size_t a) { return (uintptr_t(p) % a) == 0; }
+
+// every input array of a structure-of-arrays batch and every output array
+// aligned to a bytes
+bool all_aligned(const eig3_matrices *A, void *const *outs, size_t a)
+{
+    const int K = A->structure == EIG3_GENERAL ? 9 : 6;
+    for (int k = 0; k < K; ++k)
+        if (!aligned(A->a[k], a))
+            return false;
+    for (int e = 0; e < 3; ++e)
+        if (!aligned(outs[e], a))
+            return false;
+    return true;
+}
 
 // common validation of the matrix batch; K = number of stored entries
 int check_matrices(const eig3_matrices *A)
@@ -930,10 +1006,19 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
                                    A->n, in, out);
         });
     };
-    if (A->dtype == EIG3_F32)
+    if (A->dtype == EIG3_F32 && A->layout == EIG3_SOA && out_layout == EIG3_SOA && EIG3_F32_PAIRS &&
+        all_aligned(A, outs, 8)) {
+        const In9<float> in = inputs_of<float>(A);
+        const OutK<float, 3> out = out_slots<float, 3>(outs, nout);
+        const dim3 g2(unsigned(grid_for(A->n, 2 * kBlock)));
+        dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto, auto Acc) {
+            hipLaunchKernelGGL((k_eigvals_f32x2<S.value, Acc.value>), g2, block, 0, stream, A->n, in, out);
+        });
+    } else if (A->dtype == EIG3_F32) {
         launch(float{}, [](int s, int l, int acc, auto f) { dispatch_sla(s, l, acc, f); });
-    else
+    } else {
         launch(double{}, [](int s, int l, int acc, auto f) { dispatch_sla4(s, l, acc, f); });
+    }
     return launched();
 }
 

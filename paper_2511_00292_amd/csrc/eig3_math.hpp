@@ -948,33 +948,26 @@ __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
 // Eigenvalues in binary32 from binary64 invariants.
 __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float &l1, float &l2, float &l3)
 {
-    // The angle pair (sqrt(27 Delta), 27 |J3|) is scaled by one exact power of
-    // two 2^-e so that its larger member lies in [1/2, 1): with x < 2^ex and
-    // 27 Delta < 2^ed, e = max(ex, ceil(ed / 2)).  The square root is then
-    // taken in binary32 on a value below 1 (in [1/4, 1) when it sets the
-    // scale; a smaller one only means a small angle), so the hardware square
-    // root (1 ulp) serves.
-    // A zero member takes no part in the choice (its frexp exponent, 0, would
-    // otherwise outvote a tiny partner and leave it subnormal in binary32).
+    // The square roots sqrt(27 Delta) and r = sqrt(J2 / 3) are taken by the
+    // hardware binary64 square root, an approximation with relative error
+    // below 2^-25 over the whole binary64 range (measured on gfx950; a binary32
+    // result needs 2^-24), so no range reduction is needed.  The angle pair
+    // (sqrt(27 Delta), 27 |J3|) is then scaled by one exact power of two that
+    // puts its larger member in [1/2, 1) before it is rounded to binary32 (a
+    // smaller member that underflows there only means an angle below 2^-126).
     // (NaN in J2 or Delta comes only from NaN or Inf entries, which make J3
     // NaN too; the J3 test below carries it to the output, so plain max
     // clamps suffice here)
-    const double d = 27.0 * fmax(v.disc, 0.0);
+    const double y = __builtin_amdgcn_sqrt(27.0 * fmax(v.disc, 0.0));
     const double x = 27.0 * fabs(v.j3);
-    constexpr int kNone = -4096;
-    const int ex = x > 0.0 ? __builtin_amdgcn_frexp_exp(x) : kNone;
-    const int ed = d > 0.0 ? __builtin_amdgcn_frexp_exp(d) : kNone;
-    const int e = max(ex, (ed + 1) >> 1);
-    const float yf = __builtin_amdgcn_sqrtf(float(ldexp(d, -2 * e)));
+    const int e = __builtin_amdgcn_frexp_exp(fmax(x, y));
+    const float yf = float(ldexp(y, -e));
     const float xf = float(ldexp(x, -e));
     float psi = atan2_nonneg<false>(yf, xf);
     psi = v.j3 == v.j3 ? psi : float(v.j3); // NaN in J3 reaches the eigenvalues
     float s, c;
     sincos_sixth<false>(psi * (1.0f / 3.0f), s, c);
-    // r = sqrt(J2 / 3) the same way: q 2^-2k in [1/4, 1), r = sqrt(that) 2^k
-    const double q = fmax(v.j2, 0.0) * kThird;
-    const int k = (__builtin_amdgcn_frexp_exp(q) + 1) >> 1;
-    const float r = ldexpf(__builtin_amdgcn_sqrtf(float(ldexp(q, -2 * k))), k);
+    const float r = float(__builtin_amdgcn_sqrt(fmax(v.j2, 0.0) * kThird));
     const float mean = float(v.i1 * kThird);
     const float a1 = -r * fma_(float(kSqrt3), s, c);
     const float a2 = r * fma_(float(kSqrt3), s, -c);

@@ -79,6 +79,36 @@ def test_f32_ragged(eig3, n):
             check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"f32 ragged n={n} {acc} {layout}")
 
 
+@pytest.mark.parametrize("structure", ["symmetric", "general"])
+@pytest.mark.parametrize("acc", ACCS)
+def test_f32_two_per_lane(eig3, structure, acc):
+    """binary32 structure-of-arrays eigenvalues with every array 8-byte aligned
+    take two adjacent matrices per lane in spans of 512, with a one-per-lane
+    ragged last span; arrays that are only 4-byte aligned take the
+    one-per-lane kernel.  The arithmetic per matrix is the same, so both give
+    bitwise equal eigenvalues, and both meet the bound."""
+    import torch
+    for n in (1, 2, 511, 512, 513, 1024 + 37, 5 * 512):
+        if structure == "symmetric":
+            a32 = w.config4(n, seed=95)["s"]
+            t = Truth(w.symmetric_to_general(a32.astype(np.float64)), np.ones(n))
+        else:
+            c = w.config1(n, seed=95)
+            a32 = c["a"].astype(np.float32)
+            t = Truth(a32.astype(np.float64), c["kappa"])
+        aligned = [x.clone() for x in upload(a32, "soa")]  # own allocations
+        shifted = []
+        for x in aligned:  # the same values one element into a larger buffer
+            buf = torch.empty(n + 1, dtype=torch.float32, device=x.device)
+            buf[1:] = x
+            shifted.append(buf[1:])
+        assert all(x.data_ptr() % 8 == 0 for x in aligned) and shifted[0].data_ptr() % 8 == 4
+        pair = download_lam(eig3.eig3_eigvals(aligned, structure, acc, "soa"))
+        one = download_lam(eig3.eig3_eigvals(shifted, structure, acc, "soa"))
+        assert np.array_equal(pair, one, equal_nan=True), (structure, acc, n)
+        check(lam_errors(t, pair), t.bound_lam(EPS32), what=f"f32 two per lane {structure} {acc} n={n}")
+
+
 @pytest.mark.parametrize("layout", ["soa", "aos"])
 def test_f32_backward(eig3, layout):
     """binary32 adjoint: binary64 arithmetic on the widened entries, rounded
