@@ -141,6 +141,18 @@ def stated_accuracy():
     return out
 
 
+def cpu_model() -> str:
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def settle(torch, fn, min_ms=100.0, min_calls=3):
     """Call fn (untimed) until min_ms of wall time has passed, at least
     min_calls times: after an idle stretch (host-side data generation) the GPU
@@ -400,20 +412,29 @@ def main():
         sample_n = 1 << 20
         cs = w.config5(sample_n, seed=w.SEEDS[5] + 1)
         cores = plain.max_threads()
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            plain.eigvals(cs["a"])
-            plain.eigvals_backward(cs["a"], cs["g"])
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds or reps >= 200:
-                break
-        cpu = {"value": reps * sample_n / el, "unit": "matrices/s", "cores": cores, "kind": "oracle",
+
+        def oracle_rate(threads, seconds, n):
+            a, gg = cs["a"][:n], cs["g"][:n]
+            t0 = time.perf_counter()
+            reps = 0
+            while True:
+                plain.eigvals(a, threads)
+                plain.eigvals_backward(a, gg, threads)
+                reps += 1
+                el = time.perf_counter() - t0
+                if el >= seconds:
+                    return reps, el, reps * n / el
+
+        reps, el, rate = oracle_rate(0, args.cpu_seconds, sample_n)
+        reps1, el1, rate1 = oracle_rate(1, args.cpu_seconds / 4, sample_n >> 4)
+        cpu = {"value": rate, "unit": "matrices/s", "cores": cores, "kind": "oracle",
                "sample": f"{reps} passes of forward eigvals + eigenprojector backward over {sample_n} "
-                         f"config-5 matrices (plain binary64 C of the paper's algorithms, OpenMP), "
-                         f"{el:.1f} s"}
-        log(f"cpu baseline {cpu['value'] / 1e6:.1f} M mat/s on {cores} threads")
+                         f"config-5 matrices (plain binary64 C of the paper's algorithms, OpenMP, "
+                         f"gcc -O2 -ffp-contract=off), {el:.1f} s",
+               "single_core": {"value": rate1, "unit": "matrices/s", "cores": 1,
+                               "sample": f"{reps1} passes over {sample_n >> 4} matrices, {el1:.1f} s"},
+               "cpu_model": cpu_model()}
+        log(f"cpu baseline {rate / 1e6:.1f} M mat/s on {cores} threads, {rate1 / 1e6:.2f} M mat/s on 1")
 
     out = {
         "metric": METRIC,
