@@ -222,18 +222,28 @@ int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9],
 
 /*
  * Vector-Jacobian product of eig3_matrix_function: grad_a = d<G, f(A)>/dA.
- * The derivative of a function of a matrix with distinct eigenvalues follows
- * from the same eigenprojectors (Sec. "Introduction and motivation": closed
- * forms for functions of matrices and their derivatives):
+ * The derivative of a function of a matrix follows from the same closed
+ * forms (Sec. "Introduction and motivation": closed forms for functions of
+ * matrices and their derivatives); for distinct eigenvalues it is the
+ * Daleckii-Krein sum
  *   d f(A) = sum_{k,l} Gamma_kl E_k dA E_l,  grad_a = sum_{k,l} Gamma_kl E_k^T G E_l^T,
- * Gamma_kk = f'(lambda_k), Gamma_kl = (f(lambda_k) - f(lambda_l)) / (lambda_k - lambda_l),
- * the divided differences formed from the eigenvalue gaps without
- * cancellation (exp: e^y expm1(d)/d, log: log1p(d/y)/d, sqrt: 1/(sqrt x + sqrt y)).
+ * Gamma_kk = f'(lambda_k), Gamma_kl = (f(lambda_k) - f(lambda_l)) / (lambda_k - lambda_l).
+ * It is evaluated as the equal bivariate interpolant in tensor Newton form,
+ *   grad_a = sum_{p,q <= 2} f[z0..zp, z0..zq] N_p G N_q,
+ *   N_0 = I, N_1 = A^T - z0 I, N_2 = (A^T - z0 I)(A^T - z1 I),
+ * with the nodes z0 = lambda_min, z1 = lambda_max, z2 = lambda_mid and the
+ * divided differences (up to fifth order, each eigenvalue at most twice)
+ * from cancellation-free first differences (exp: e^y expm1(d)/d, log:
+ * log1p(d/y)/d, sqrt: 1/(sqrt x + sqrt y)) by a recursion that divides by the
+ * spread wherever it can; gaps below 2^-26 of the spread take the confluent
+ * values f^(k)/k!.  So the result stays accurate as eigenvalues coalesce,
+ * with repeated eigenvalues (grad_a = f'(p) G at A = p I) and defective A
+ * included.
  * g: the upstream gradient in the structure and layout of the forward's
  * output (GENERAL: 9 entries; SYMMETRIC: dL/d of the 6 stored components).
  * grad_a: the structure and layout of A (SYMMETRIC: the derivative with
- * respect to each stored entry).  Arithmetic in binary64.  Needs distinct
- * eigenvalues; outside the domain of f the result is NaN.
+ * respect to each stored entry).  Arithmetic in binary64.  Outside the domain
+ * of f the result is NaN.
  */
 int eig3_matrix_function_backward(const eig3_matrices *A, int32_t fn, const void *const g[9], void *const grad_a[9],
                                   hipStream_t stream);

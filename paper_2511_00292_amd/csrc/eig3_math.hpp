@@ -1193,54 +1193,135 @@ template <int Fn> __device__ __forceinline__ void matrix_function_general(const 
 }
 
 
-// The vector-Jacobian product of f(A): with d f(A) = sum_{k,l} Gamma_kl E_k dA
-// E_l (Daleckii-Krein; Gamma_kk = f'(lambda_k), Gamma_kl the divided
-// differences), grad = sum_{k,l} Gamma_kl E_k^T G E_l^T.  G and grad are 3x3
-// row-major.
+// C = A B for 3x3 row-major matrices
+__device__ __forceinline__ void matmul3(const double A[9], const double B[9], double C[9])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            C[3 * r + c] = fma_(A[3 * r], B[c], fma_(A[3 * r + 1], B[3 + c], A[3 * r + 2] * B[6 + c]));
+}
+
+// f^(k)(x) / k! for k = 1..5, given fx = f(x)
+template <int Fn> __device__ __forceinline__ double taylor_coefficient(int k, double x, double fx)
+{
+    if constexpr (Fn == EIG3_EXP) {
+        constexpr double inv_fact[6] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0};
+        return fx * inv_fact[k];
+    } else if constexpr (Fn == EIG3_LOG) {
+        // (-1)^(k+1) / (k x^k)
+        const double r = 1.0 / x;
+        double p = r;
+        for (int j = 1; j < k; ++j)
+            p *= -r;
+        return p / double(k);
+    } else {
+        // binomial(1/2, k) x^(1/2 - k)
+        constexpr double binom[6] = {1.0, 0.5, -0.125, 0.0625, -0.0390625, 0.02734375};
+        const double r = 1.0 / x;
+        double p = fx;
+        for (int j = 0; j < k; ++j)
+            p *= r;
+        return binom[k] * p;
+    }
+}
+
+// The vector-Jacobian product of f(A), grad = d<G, f(A)>/dA = L_f(A^T)[G],
+// the Frechet derivative of f at A^T applied to G (for f with real Taylor
+// coefficients).  With X = A^T and the eigenvalues as nodes in the order
+// z0 = lambda_min, z1 = lambda_max, z2 = lambda_mid, the Daleckii-Krein sum
+// sum_{k,l} f[lambda_k, lambda_l] E_k G E_l is the bivariate interpolant of
+// f[x, y] in tensor Newton form,
+//   grad = sum_{p,q <= 2} f[z0..zp, z0..zq] N_p G N_q,
+//   N_0 = I, N_1 = X - z0 I, N_2 = (X - z0 I)(X - z1 I),
+// whose coefficients are divided differences of f over the merged node lists
+// (each eigenvalue at most twice).  They are formed by the recursion that
+// divides by the largest gap z1 - z0 wherever both ends are present; the
+// divisions by the smaller gaps (z2 - z0, z1 - z2) enter only coefficients
+// of N_2, which shrinks with those gaps, so the result stays accurate as
+// eigenvalues coalesce.  A gap below 2^-26 of the spread is treated as zero
+// (the confluent value f^(k)/k! at the end node: an error of second order in
+// the gap after the factor N_2), as is a zero spread.  N_1 and N_2 come from
+// the deviatoric part of X (diagonal differences), so the isotropic part
+// cancels exactly.  G and grad are 3x3 row-major.
 template <int Fn>
 __device__ __forceinline__ void matrix_function_backward_general(const Gen &A, const Inv &v, const double G[9],
                                                                  double grad[9])
 {
     const Trig t = trig_from_invariants<false>(v);
-    double E[27];
-    eigenprojectors_general(A, t, E);
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
-    const double lam[3] = {t.mean + m1, t.mean + m2, t.mean + m3};
-    const double f[3] = {scalar_function<Fn>(lam[0]), scalar_function<Fn>(lam[1]), scalar_function<Fn>(lam[2])};
     const Gaps gp = gaps_from_trig(t);
-    const double g12 = divided_difference<Fn>(lam[0], f[1], f[0], gp.e12);
-    const double g13 = divided_difference<Fn>(lam[0], f[2], f[0], gp.e13);
-    const double g23 = divided_difference<Fn>(lam[1], f[2], f[1], gp.e23);
-    const double gam[9] = {divided_difference<Fn>(lam[0], f[0], f[0], 0.0), g12, g13,
-                           g12, divided_difference<Fn>(lam[1], f[1], f[1], 0.0), g23,
-                           g13, g23, divided_difference<Fn>(lam[2], f[2], f[2], 0.0)};
+    const double z0 = t.mean + m1, z1 = t.mean + m3, z2 = t.mean + m2;
+    const double f0 = scalar_function<Fn>(z0), f1 = scalar_function<Fn>(z1), f2 = scalar_function<Fn>(z2);
+    const double spread = gp.e13;
+    const bool iso = spread == 0.0;
+    constexpr double kTau = 0x1p-26;
+    const bool low = gp.e12 <= kTau * spread;  // z2 merges with z0
+    const bool high = gp.e23 <= kTau * spread; // z2 merges with z1
+    // first order (cancellation-free formulas, exact zero gaps included)
+    const double d01 = divided_difference<Fn>(z0, f1, f0, spread);     // f[z0, z1]
+    const double d02 = divided_difference<Fn>(z0, f2, f0, gp.e12);     // f[z0, z2]
+    const double d12 = divided_difference<Fn>(z2, f1, f2, gp.e23);     // f[z2, z1]
+    const double c00 = taylor_coefficient<Fn>(1, z0, f0);              // f[z0, z0]
+    const double c11 = taylor_coefficient<Fn>(1, z1, f1);              // f[z1, z1]
+    const double c22 = taylor_coefficient<Fn>(1, z2, f2);              // f[z2, z2]
+    // D(m0, m1, m2): divided difference with z0, z1, z2 taken m0, m1, m2 times
+    auto ruleA = [&](double without_z0, double without_z1, int order) {
+        return iso ? taylor_coefficient<Fn>(order, z0, f0) : (without_z0 - without_z1) / spread;
+    };
+    auto ruleB = [&](double without_z0, double without_z2, int order) {
+        return low ? taylor_coefficient<Fn>(order, z0, f0) : (without_z0 - without_z2) / gp.e12;
+    };
+    auto ruleC = [&](double without_z1, double without_z2, int order) {
+        return high ? taylor_coefficient<Fn>(order, z1, f1) : (without_z1 - without_z2) / (-gp.e23);
+    };
+    const double D210 = ruleA(d01, c00, 2);
+    const double D120 = ruleA(c11, d01, 2);
+    const double D220 = ruleA(D120, D210, 3);
+    const double D111 = ruleA(d12, d02, 2);
+    const double D201 = ruleB(d02, c00, 2);
+    const double D211 = ruleA(D111, D201, 3);
+    const double D021 = ruleC(d12, c11, 2);
+    const double D121 = ruleA(D021, D111, 3);
+    const double D221 = ruleA(D121, D211, 4);
+    const double D012 = ruleC(c22, d12, 2);
+    const double D102 = ruleB(c22, d02, 2);
+    const double D022 = ruleC(D012, D021, 3);
+    const double D112 = ruleA(D012, D102, 3);
+    const double D202 = ruleB(D102, D201, 3);
+    const double D122 = ruleA(D022, D112, 4);
+    const double D212 = ruleA(D112, D202, 4);
+    const double D222 = ruleA(D122, D212, 5);
+    const double F00 = c00, F10 = D210, F11 = D220, F20 = D211, F21 = D221, F22 = D222;
+    // N1 = X - z0 I and X - z1 I from the deviatoric part of X = A^T
+    const Diag g = diag_part(A.a00, A.a11, A.a22);
+    const double s00 = (g.d0 + g.d1) * kThird, s11 = (g.d2 - g.d0) * kThird, s22 = -(g.d1 + g.d2) * kThird;
+    const double N1[9] = {s00 - m1, A.a10, A.a20, A.a01, s11 - m1, A.a21, A.a02, A.a12, s22 - m1};
+    const double M3[9] = {s00 - m3, A.a10, A.a20, A.a01, s11 - m3, A.a21, A.a02, A.a12, s22 - m3};
+    double N2[9], U1[9], U2[9];
+    matmul3(N1, M3, N2);
+    matmul3(N1, G, U1);
+    matmul3(N2, G, U2);
+    double V[9], W1[9], W2[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e)
-        grad[e] = 0.0;
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        // H = G E_l^T
-        double H[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                H[3 * r + c] = fma_(G[3 * r], E[9 * l + 3 * c],
-                                    fma_(G[3 * r + 1], E[9 * l + 3 * c + 1], G[3 * r + 2] * E[9 * l + 3 * c + 2]));
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double w = gam[3 * k + l];
-            // grad += w E_k^T H
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    grad[3 * r + c] = fma_(w, fma_(E[9 * k + r], H[c], fma_(E[9 * k + 3 + r], H[3 + c],
-                                                                            E[9 * k + 6 + r] * H[6 + c])),
-                                           grad[3 * r + c]);
-        }
+    for (int e = 0; e < 9; ++e) {
+        V[e] = fma_(F00, G[e], fma_(F10, U1[e], F20 * U2[e]));
+        W1[e] = fma_(F10, G[e], fma_(F11, U1[e], F21 * U2[e]));
+        W2[e] = fma_(F20, G[e], fma_(F21, U1[e], F22 * U2[e]));
     }
+    // grad = V + W1 N1 + W2 N2
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double acc = V[3 * r + c];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                acc = fma_(W1[3 * r + k], N1[3 * k + c], fma_(W2[3 * r + k], N2[3 * k + c], acc));
+            grad[3 * r + c] = acc;
+        }
 }
 
 } // namespace eig3

@@ -2,7 +2,9 @@
 evaluated as the interpolation polynomial in Newton form, against the exact
 oracle (80-digit eigenprojectors and f), on general matrices with separated
 spectra, on symmetric positive definite ones and on nearly isotropic ones;
-repeated eigenvalues; identities and the domain rule."""
+repeated eigenvalues; identities and the domain rule.  The adjoint
+(eig3_matrix_function_backward) likewise, including nearly and exactly
+repeated eigenvalues and defective matrices."""
 import numpy as np
 import pytest
 
@@ -206,3 +208,93 @@ def test_autograd_against_torch_matrix_exp(eig3):
     assert torch.all((f1 - f2).detach().abs().amax(dim=(1, 2)) <= 1e-11 * scale_f)
     scale_g = a2.grad.abs().amax(dim=(1, 2))
     assert torch.all((a1.grad - a2.grad).abs().amax(dim=(1, 2)) <= 1e-10 * scale_g)
+
+
+@pytest.mark.parametrize("fn", ["exp", "log", "sqrt"])
+def test_backward_coalescing_eigenvalues(eig3, fn):
+    """The adjoint as eigenvalues coalesce, against the exact Daleckii-Krein
+    product at 80 digits: nearly isotropic p I + delta S, a nearly double root
+    at either end of the spectrum (symmetric), and nearly double roots of
+    nonsymmetric matrices (kappa(V) = 10)."""
+    rng = np.random.default_rng(102)
+
+    def rot():
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        return q * np.sign(np.diag(r))
+
+    mats = []
+    for delta in (1e-4, 1e-9, 1e-13):
+        for _ in range(20):
+            p = rng.uniform(0.5, 2.0)
+            sm = rng.standard_normal((3, 3))
+            mats.append((p * np.eye(3) + delta * (sm + sm.T) / 2).ravel())
+    for eps in (1e-7, 1e-13):
+        for _ in range(20):
+            q, b = rot(), rng.uniform(0.5, 1.5)
+            c = b + rng.uniform(0.5, 2.0)
+            mats.append((q @ np.diag([b, b * (1 + eps), c]) @ q.T).ravel())
+            mats.append((q @ np.diag([b, c, c * (1 + eps)]) @ q.T).ravel())
+            v = rot() @ np.diag([1.0, 10 ** -0.5, 0.1]) @ rot().T
+            mats.append((v @ np.diag([b, b * (1 + eps), b + 1.0]) @ np.linalg.inv(v)).ravel())
+    a = np.array(mats)
+    g = rng.standard_normal(a.shape)
+    res = download_matrix(eig3.eig3_matrix_function_backward(upload(a, "soa"), upload(g, "soa"), fn), 9)
+    for m in range(len(a)):
+        ref = np.array(exact.matrix_function_vjp(a[m], fn, g[m]))
+        assert _rel(res[m], ref) <= 1e-13, (fn, m)
+
+
+def test_backward_repeated_and_defective(eig3):
+    """Exactly repeated eigenvalues of diagonal matrices, where the adjoint is
+    f[d_i, d_j] G_ij (f' on equal entries), for exp, log and sqrt; and
+    d<G, exp(A)>/dA for single Jordan blocks p I + N against torch's autograd
+    of torch.linalg.matrix_exp (binary64 on the CPU)."""
+    import torch
+    rng = np.random.default_rng(103)
+    diag = np.array([[1.0, 1.0, 1.0], [2.5, 2.5, 2.5], [1.0, 1.0, 2.0], [3.0, 0.5, 3.0], [0.25, 4.0, 4.0]])
+    a = np.zeros((len(diag), 9))
+    a[:, [0, 4, 8]] = diag
+    g = rng.standard_normal(a.shape)
+    funcs = {"exp": (np.exp, np.exp), "log": (np.log, lambda x: 1 / x), "sqrt": (np.sqrt, lambda x: 0.5 / np.sqrt(x))}
+    for fn, (f, df) in funcs.items():
+        res = download_matrix(eig3.eig3_matrix_function_backward(upload(a, "soa"), upload(g, "soa"), fn), 9)
+        ref = np.zeros_like(a)
+        for m, d in enumerate(diag):
+            for i in range(3):
+                for j in range(3):
+                    x, y = d[i], d[j]
+                    ref[m, 3 * i + j] = g[m, 3 * i + j] * (df(x) if x == y else (f(x) - f(y)) / (x - y))
+        assert np.abs(res - ref).max() <= 1e-15 * np.abs(ref).max() * 8, fn
+    p = rng.uniform(0.5, 2.0, 64)
+    nil = np.zeros((64, 3, 3))
+    nil[:, 0, 1], nil[:, 0, 2], nil[:, 1, 2] = rng.uniform(-3, 3, (3, 64))
+    nil[32:] = nil[32:].transpose(0, 2, 1)
+    a = (p[:, None, None] * np.eye(3) + nil).reshape(-1, 9)
+    g = rng.standard_normal(a.shape)
+    res = download_matrix(eig3.eig3_matrix_function_backward(upload(a, "soa"), upload(g, "soa"), "exp"), 9)
+    at = torch.tensor(a.reshape(-1, 3, 3), requires_grad=True)
+    torch.linalg.matrix_exp(at).backward(torch.tensor(g.reshape(-1, 3, 3)))
+    ref = at.grad.numpy().reshape(-1, 9)
+    err = np.abs(res - ref).max(1) / np.abs(ref).max(1)
+    assert err.max() <= 1e-13, (int(err.argmax()), err.max())
+
+
+def test_autograd_isotropic_log(eig3):
+    """Hencky-type use: log of (nearly) isotropic stretch tensors through the
+    autograd Function stays finite and matches the exact product; at A = p I
+    the gradient of <G, log A> is G / p."""
+    import torch
+    a = torch.eye(3, dtype=torch.float64, device="cuda:0").repeat(8, 1, 1) * 1.5
+    noise = np.random.default_rng(104).standard_normal((4, 3, 3))
+    a[4:] += 1e-10 * torch.tensor(noise + noise.transpose(0, 2, 1), device="cuda:0")  # real spectrum
+    a = a.requires_grad_(True)
+    wgt = torch.tensor(np.random.default_rng(105).standard_normal((8, 3, 3)), dtype=torch.float64, device="cuda:0")
+    (eig3.matrix_function(a, "log") * wgt).sum().backward()
+    grad = a.grad.cpu().numpy()
+    assert np.isfinite(grad).all()
+    ref = wgt[:4].cpu().numpy() / 1.5
+    assert np.abs(grad[:4] - ref).max() <= 4 * 2.0**-52 * np.abs(ref).max()
+    ad = a.detach().cpu().numpy().reshape(-1, 9)
+    for m in range(4, 8):
+        ref = np.array(exact.matrix_function_vjp(ad[m], "log", wgt[m].cpu().numpy().ravel()))
+        assert _rel(grad[m].ravel(), ref) <= 1e-13, m
