@@ -114,6 +114,25 @@ __device__ __forceinline__ Diag diag_part(double a00, double a11, double a22)
     return g;
 }
 
+// For the compensated evaluations: d0 and d2 as rounded differences and
+// d1 = d0 + d2 exactly, as d1 + d1l.  The three rounded differences
+// A00 - A11, A00 - A22, A11 - A22 need not satisfy d1 = d0 + d2, and then they
+// are the diagonal differences of no matrix: near a triple root the factors
+// of Delta, evaluated exactly from such a triple, miss Delta by far more than
+// the stability bound allows.  A consistent triple is the exact difference
+// data of a diagonal perturbed by one rounding, a backward error.
+template <class T> struct DiagC {
+    T d0, d1, d2, d1l;
+};
+template <class T> __device__ __forceinline__ DiagC<T> diag_consistent(T a00, T a11, T a22)
+{
+    DiagC<T> g;
+    g.d0 = a00 - a11;
+    g.d2 = a11 - a22;
+    two_sum(g.d0, g.d2, g.d1, g.d1l);
+    return g;
+}
+
 constexpr double kSixth = 1.0 / 6.0;
 constexpr double kThird = 1.0 / 3.0;
 constexpr double kTwentySeventh = 1.0 / 27.0;
@@ -279,16 +298,21 @@ __device__ __forceinline__ Inv invariants_symmetric_fma(const Sym &S)
 // exactly, as hi + lo.
 template <class T> struct DxPairs {
     T M01, M02, M10, M12, M20, M21, d0, d1, d2;
+    T d1l; // d1 = d0 + d2 exactly as d1 + d1l (see diag_consistent)
     PairT<T> d0d1, d1d2, d0d2;
     PairT<T> m01m12, m02m10, m01m02, m01m01, m02m02, m01m21, m02m21, m02m12, m01m10, m12m12, m02m20, m12m21;
 };
 
 template <class T>
 __device__ __forceinline__ DxPairs<T> dx_pairs(T M01, T M02, T M10, T M12, T M20, T M21, T d0, T d1, T d2,
-                                               const PairT<T> &d0d1, const PairT<T> &d1d2, const PairT<T> &d0d2)
+                                               const PairT<T> &d0d1, const PairT<T> &d1d2, const PairT<T> &d0d2,
+                                               T d1l = T(0))
 {
-    DxPairs<T> p{M01, M02, M10, M12, M20, M21, d0, d1, d2, d0d1, d1d2, d0d2, {}, {}, {}, {}, {}, {}, {}, {}, {}, {},
-                 {}, {}};
+    DxPairs<T> p{M01, M02, M10, M12, M20, M21, d0, d1, d2, d1l, d0d1, d1d2, d0d2, {}, {}, {}, {}, {}, {}, {}, {}, {},
+                 {}, {}, {}};
+    // d0 d1 and d1 d2 with d1's low part (its product is of order eps^2)
+    p.d0d1.lo = fma_(d0, d1l, p.d0d1.lo);
+    p.d1d2.lo = fma_(d1l, d2, p.d1d2.lo);
     p.m01m12 = pair(M01, M12);
     p.m02m10 = pair(M02, M10);
     p.m01m02 = pair(M01, M02);
@@ -317,6 +341,7 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPair
         a.add(neg(p.m02m02), p.M21);
     } else if constexpr (I == 2) {
         a.first(p.m01m21, p.d1);
+        a.c = fma_(p.m01m21.hi, p.d1l, a.c);
         a.add(neg(p.m01m01), p.M20);
         a.add(p.m02m21, p.M21);
     } else if constexpr (I == 3) {
@@ -325,6 +350,7 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPair
         a.add(neg(p.m02m02), p.M10);
     } else if constexpr (I == 4) {
         a.first(p.m01m12, p.d1);
+        a.c = fma_(p.m01m12.hi, p.d1l, a.c);
         a.add(neg(p.m01m02), p.M10);
         a.add(p.m02m12, p.M21);
     } else if constexpr (I == 5) {
@@ -338,6 +364,7 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPair
     } else if constexpr (I == 7) {
         a.first(p.d0d1, p.M12);
         a.add(neg(p.m02m10), p.d1);
+        a.c = fma_(-p.m02m10.hi, p.d1l, a.c);
         a.add(p.m01m10, p.M12);
         a.add(neg(p.m12m12), p.M21);
     } else if constexpr (I == 8) {
@@ -353,6 +380,7 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPair
     } else if constexpr (I == 10) {
         a.first(p.d1d2, p.M01);
         a.add(p.m02m21, p.d1);
+        a.c = fma_(p.m02m21.hi, p.d1l, a.c);
         a.add(p.m01m12, p.M21);
         a.add(neg(p.m01m01), p.M10);
     } else if constexpr (I == 11) {
@@ -369,6 +397,7 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPair
         a.first(p.d0d1, p.d2);
         a.add(neg(p.m01m10), p.d0);
         a.add(p.m02m20, p.d1);
+        a.c = fma_(p.m02m20.hi, p.d1l, a.c);
         a.add(neg(p.m12m21), p.d2);
     }
     a.split(hi, lo);
@@ -385,9 +414,9 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_all(const DxPa
 template <class T>
 __device__ __forceinline__ void dx_comp(T M01, T M02, T M10, T M12, T M20, T M21, T d0, T d1, T d2,
                                         const PairT<T> &d0d1, const PairT<T> &d1d2, const PairT<T> &d0d2,
-                                        T rh[14], T rl[14])
+                                        T rh[14], T rl[14], T d1l = T(0))
 {
-    dx_comp_all<0>(dx_pairs(M01, M02, M10, M12, M20, M21, d0, d1, d2, d0d1, d1d2, d0d2), rh, rl);
+    dx_comp_all<0>(dx_pairs(M01, M02, M10, M12, M20, M21, d0, d1, d2, d0d1, d1d2, d0d2, d1l), rh, rl);
 }
 
 // sum_i w_i u_i v_i, u = dx(A) and v = dx(A^T) as hi + lo, compensated;
@@ -435,8 +464,8 @@ __device__ __forceinline__ double sum_wuv_comp(const DxPairs<double> &pu, const 
 __device__ __forceinline__ Inv invariants_general_comp(const Gen &A)
 {
     Inv r;
-    const Diag g = diag_part(A.a00, A.a11, A.a22);
-    r.i1 = g.i1;
+    r.i1 = diag_part(A.a00, A.a11, A.a22).i1;
+    const DiagC<double> g = diag_consistent(A.a00, A.a11, A.a22);
     // J2: the sum of squares needs no compensation; the off-diagonal products do
     {
         const Pair p01 = pair(A.a01, A.a10), p02 = pair(A.a02, A.a20), p12 = pair(A.a12, A.a21);
@@ -446,7 +475,7 @@ __device__ __forceinline__ Inv invariants_general_comp(const Gen &A)
         two_sum(s, p12.hi, t, e2);
         double u, e3;
         two_sum(t, sq, u, e3);
-        r.j2 = u + (((e1 + e2) + e3) + ((p01.lo + p02.lo) + p12.lo));
+        r.j2 = u + (((e1 + e2) + e3) + fma_(g.d1 * kThird, g.d1l, (p01.lo + p02.lo) + p12.lo));
     }
     // J3: 27 J3 = 27 offdiag + 9 mixed - t1 t2 t3, accumulated compensated
     // (the t's are rounded sums of two differences; their rounding is the
@@ -466,8 +495,8 @@ __device__ __forceinline__ Inv invariants_general_comp(const Gen &A)
     {
         const Pair d0d1 = pair(g.d0, g.d1), d1d2 = pair(g.d1, g.d2), d0d2 = pair(g.d0, g.d2);
         r.disc = sum_wuv_comp(
-            dx_pairs(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2),
-            dx_pairs(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2));
+            dx_pairs(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, g.d1l),
+            dx_pairs(A.a10, A.a20, A.a01, A.a21, A.a02, A.a12, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, g.d1l));
     }
     return r;
 }
@@ -478,8 +507,8 @@ __device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
     // keeps the final sum a sum of nonnegative terms
     Gen A{S.s00, S.s01, S.s02, S.s01, S.s11, S.s12, S.s02, S.s12, S.s22};
     Inv r;
-    const Diag g = diag_part(S.s00, S.s11, S.s22);
-    r.i1 = g.i1;
+    r.i1 = diag_part(S.s00, S.s11, S.s22).i1;
+    const DiagC<double> g = diag_consistent(S.s00, S.s11, S.s22);
     const double q01 = S.s01 * S.s01, q02 = S.s02 * S.s02, q12 = S.s12 * S.s12;
     r.j2 = fma_(fma_(g.d0, g.d0, fma_(g.d1, g.d1, g.d2 * g.d2)), kSixth, q01 + (q02 + q12));
     {
@@ -495,7 +524,7 @@ __device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
     {
         const Pair d0d1 = pair(g.d0, g.d1), d1d2 = pair(g.d1, g.d2), d0d2 = pair(g.d0, g.d2);
         double uh[14], ul[14];
-        dx_comp(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, uh, ul);
+        dx_comp(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, uh, ul, g.d1l);
         // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2 (+ 9 u1^2, u1 ~ 0)
         double s = 0.0, c = 0.0;
         const double w[14] = {9, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
@@ -831,7 +860,7 @@ struct InvW {
 // exactly in binary64 (J2 by 2^2s, J3 by 2^3s, Delta by 2^6s).  Powers of two
 // commute with every rounding in between.
 struct DevF32 {
-    float d0, d1, d2;
+    float d0, d1, d2, d1l; // d1 = d0 + d2 exactly as d1 + d1l
     float o[6]; // general: A01 A02 A10 A12 A20 A21; symmetric: S01 S02 S12
     int sc;     // the data are the matrix's times 2^-sc
 };
@@ -839,7 +868,8 @@ struct DevF32 {
 template <int KO> __device__ __forceinline__ DevF32 dev_data_f32(float a00, float a11, float a22, const float *off)
 {
     DevF32 v;
-    const float d[3] = {a00 - a11, a00 - a22, a11 - a22};
+    const DiagC<float> g = diag_consistent(a00, a11, a22);
+    const float d[3] = {g.d0, g.d1, g.d2};
     float m = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fabsf(d[2]));
 #pragma unroll
     for (int k = 0; k < KO; ++k)
@@ -848,6 +878,7 @@ template <int KO> __device__ __forceinline__ DevF32 dev_data_f32(float a00, floa
     v.d0 = ldexpf(d[0], -v.sc);
     v.d1 = ldexpf(d[1], -v.sc);
     v.d2 = ldexpf(d[2], -v.sc);
+    v.d1l = ldexpf(g.d1l, -v.sc);
 #pragma unroll
     for (int k = 0; k < KO; ++k)
         v.o[k] = ldexpf(off[k], -v.sc);
@@ -892,8 +923,8 @@ __device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
     {
         const PairT<float> d0d1 = pair(d0, d1), d1d2 = pair(d1, d2), d0d2 = pair(d0, d2);
         float uh[14], ul[14], vh[14], vl[14];
-        dx_comp<float>(a01, a02, a10, a12, a20, a21, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul);
-        dx_comp<float>(a10, a20, a01, a21, a02, a12, d0, d1, d2, d0d1, d1d2, d0d2, vh, vl);
+        dx_comp<float>(a01, a02, a10, a12, a20, a21, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul, v.d1l);
+        dx_comp<float>(a10, a20, a01, a21, a02, a12, d0, d1, d2, d0d1, d1d2, d0d2, vh, vl, v.d1l);
         const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
         double disc = 0.0;
 #pragma unroll
@@ -928,7 +959,7 @@ __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
     {
         const PairT<float> d0d1 = pair(d0, d1), d1d2 = pair(d1, d2), d0d2 = pair(d0, d2);
         float uh[14], ul[14];
-        dx_comp<float>(s01, s02, s01, s12, s02, s12, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul);
+        dx_comp<float>(s01, s02, s01, s12, s02, s12, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul, v.d1l);
         // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2
         const double w[14] = {0, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
         double disc = 0.0;

@@ -81,11 +81,14 @@ def test_config2_buckets(eig3, plain, c2, acc, kappa):
     bl, bi = t.bound_lam()[sel], t.bound_inv()[sel]
     al = lam_errors(t, o1_lam)[sel]
     ai = inv_errors(t, o1_inv)[sel]
-    if kappa <= 10.0:
+    # compensated: within 8x the bounds at every kappa (consistent diagonal
+    # differences and error-free products); fma: the paper's class, G2 where
+    # the paper's own algorithm exceeds the bounds
+    if kappa <= 10.0 or acc == "compensated":
         check(el, np.broadcast_to(bl, el.shape), what=f"config2 eigvals kappa={kappa} {acc} (G1)")
     else:
         check_g2(el, bl, al, what=f"config2 eigvals kappa={kappa} {acc} (G2)", pool=True)
-    if kappa == 1.0 or (kappa == 10.0 and acc == "compensated"):
+    if kappa == 1.0 or acc == "compensated":
         check(ei, bi, what=f"config2 invariants kappa={kappa} {acc} (G1)")
     else:
         check_g2(ei, bi, ai, what=f"config2 invariants kappa={kappa} {acc} (G2)")
@@ -109,8 +112,10 @@ def test_config5_forward(eig3, plain, c5, acc):
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], "aos"), "general", acc, "aos"))
     el = lam_errors(t, lam)
     bl = np.broadcast_to(t.bound_lam(), el.shape)
-    well = c["kappa"] <= 10
-    check(el[well], bl[well], what=f"config5 eigvals kappa<=10 {acc} (G1)")
+    well = (c["kappa"] <= 10) | (acc == "compensated")
+    check(el[well], bl[well], what=f"config5 eigvals kappa<=10 or compensated {acc} (G1)")
+    if well.all():
+        return
     al = lam_errors(t, plain.eigvals(c["a"]))
     check_g2(el[~well], bl[~well], al[~well], what=f"config5 eigvals kappa>10 {acc} (G2)", pool=True)
 

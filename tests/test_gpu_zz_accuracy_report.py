@@ -60,6 +60,31 @@ def test_accuracy_report(plain_oracle):
                  **{k: _ratios(gi[:, j], bi[:, j]) for j, k in enumerate(("I1", "J2", "J3", "Delta"))}},
                 {"eigvals": _ratios(lam_errors(t2, o2l)[sel], bl),
                  **{k: _ratios(pi[:, j], bi[:, j]) for j, k in enumerate(("I1", "J2", "J3", "Delta"))}})
+    # the perturbation sweep by bucket: variant x kappa x delta range, 1024
+    # matrices per (variant, kappa), eigenvalues of both modes and of the
+    # paper's algorithm against the exact roots (max, p99, p99.99)
+    cb = w.config2(9 * 1024, seed=16)
+    tb = Truth(cb["a"], cb["kappa"])
+    ob = lam_errors(tb, plain_oracle.eigvals(cb["a"])) / tb.bound_lam()
+    gb = {acc: lam_errors(tb, download_lam(eig3.eig3_eigvals(upload(cb["a"], "soa"), "general", acc, "soa")))
+          / tb.bound_lam() for acc in ("fma", "compensated")}
+    names = {0: "diag(1, 1+d, 1+2d)", 1: "diag(1, 1, 1+d)", 2: "I + d S"}
+    edges = [1e-16, 1e-13, 1e-10, 1e-7, 1e-4, 1e-1]
+    rep["buckets"] = []
+    for v in range(3):
+        for kappa in (1.0, 10.0, 100.0):
+            for lo, hi in zip(edges[:-1], edges[1:]):
+                sel = (cb["variant"] == v) & (cb["kappa"] == kappa) & (cb["delta"] >= lo) & (cb["delta"] < hi)
+                if not sel.any():
+                    continue
+                st = {}
+                for key, r in (("gpu_fma", gb["fma"]), ("gpu_compensated", gb["compensated"]),
+                               ("paper_algorithm_plain_f64", ob)):
+                    x = r[sel].ravel()
+                    st[key] = {"max": float(x.max()), "p99": float(np.percentile(x, 99)),
+                               "p9999": float(np.percentile(x, 99.99))}
+                rep["buckets"].append({"variant": names[v], "kappa": kappa, "delta": [lo, hi],
+                                       "n": int(sel.sum()), **st})
     # config 3 (symmetric binary64) and config 4 (binary32)
     c3 = w.config3(1500, seed=14)
     a3 = w.symmetric_to_general(c3["s"])
