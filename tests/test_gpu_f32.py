@@ -178,6 +178,11 @@ def test_f32_special_matrices(eig3, acc):
     t = Truth(g[:9].astype(np.float64), np.ones(9))
     check(lam_errors(t, lam[:9]), t.bound_lam(EPS32), what=f"f32 special matrices {acc}")
     assert np.isnan(lam[9:]).all()
+    # the same matrices tiled over full 512-matrix spans of the two-per-lane
+    # kernel (and its ragged tail): the same values at every copy
+    reps = 100
+    tiled = download_lam(eig3.eig3_eigvals(upload(np.tile(g, (reps, 1)), "soa"), "general", acc, "soa"))
+    assert np.array_equal(tiled, np.tile(lam, (reps, 1)), equal_nan=True)
 
 
 @pytest.mark.parametrize("acc", ACCS)
