@@ -525,9 +525,10 @@ __device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
         const Pair d0d1 = pair(g.d0, g.d1), d1d2 = pair(g.d1, g.d2), d0d2 = pair(g.d0, g.d2);
         double uh[14], ul[14];
         dx_comp(A.a01, A.a02, A.a10, A.a12, A.a20, A.a21, g.d0, g.d1, g.d2, d0d1, d1d2, d0d2, uh, ul, g.d1l);
-        // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2 (+ 9 u1^2, u1 ~ 0)
+        // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2
+        // (u1 = M01 M12 M20 - M02 M10 M21 vanishes identically for A^T = A)
         double s = 0.0, c = 0.0;
-        const double w[14] = {9, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
+        const double w[14] = {0, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
 #pragma unroll
         for (int i = 0; i < 14; ++i) {
             if (w[i] == 0.0)
