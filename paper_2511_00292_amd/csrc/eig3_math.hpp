@@ -403,11 +403,57 @@ template <int I, class T> __device__ __forceinline__ void dx_comp_r(const DxPair
     a.split(hi, lo);
 }
 
+// r_(I+1) and r_(I+2) for I = 7, 9, 11, which share two of their four terms:
+// r8, r9 share M12 d0 d1 - M12^2 M21; r10, r11 share M01 d1 d2 - M01^2 M10;
+// r13 = -(r12's -M02 d0 d2 - M02^2 M20) + two terms.  The shared part is
+// accumulated once.
+template <int I, class T>
+__device__ __forceinline__ void dx_comp_r2(const DxPairs<T> &p, T &hi0, T &lo0, T &hi1, T &lo1)
+{
+    static_assert(I == 7 || I == 9 || I == 11, "paired factors");
+    AccT<T> a, b;
+    if constexpr (I == 7) {
+        a.first(p.d0d1, p.M12);
+        a.add(neg(p.m12m12), p.M21);
+        b = a;
+        a.add(neg(p.m02m10), p.d1);
+        a.c = fma_(-p.m02m10.hi, p.d1l, a.c);
+        a.add(p.m01m10, p.M12);
+        b.add(neg(p.m02m10), p.d0);
+        b.add(p.m02m12, p.M20);
+    } else if constexpr (I == 9) {
+        a.first(p.d1d2, p.M01);
+        a.add(neg(p.m01m01), p.M10);
+        b = a;
+        a.add(p.m02m21, p.d2);
+        a.add(p.m01m02, p.M20);
+        b.add(p.m02m21, p.d1);
+        b.c = fma_(p.m02m21.hi, p.d1l, b.c);
+        b.add(p.m01m12, p.M21);
+    } else {
+        a.first(neg(p.d0d2), p.M02);
+        a.add(neg(p.m02m02), p.M20);
+        b.s = -a.s;
+        b.c = -a.c;
+        a.add(p.m01m12, p.d0);
+        a.add(p.m02m12, p.M21);
+        b.add(p.m01m12, p.d2);
+        b.add(neg(p.m01m02), p.M10);
+    }
+    a.split(hi0, lo0);
+    b.split(hi1, lo1);
+}
+
 template <int I, class T> __device__ __forceinline__ void dx_comp_all(const DxPairs<T> &p, T rh[14], T rl[14])
 {
-    dx_comp_r<I>(p, rh[I], rl[I]);
-    if constexpr (I < 13)
-        dx_comp_all<I + 1>(p, rh, rl);
+    if constexpr (I == 7 || I == 9 || I == 11) {
+        dx_comp_r2<I>(p, rh[I], rl[I], rh[I + 1], rl[I + 1]);
+        dx_comp_all<I + 2>(p, rh, rl);
+    } else {
+        dx_comp_r<I>(p, rh[I], rl[I]);
+        if constexpr (I < 13)
+            dx_comp_all<I + 1>(p, rh, rl);
+    }
 }
 
 // all fourteen r_i of dx, compensated
@@ -423,14 +469,10 @@ __device__ __forceinline__ void dx_comp(T M01, T M02, T M10, T M12, T M20, T M21
 // weights scale exactly except 6 and 9, which are applied as exact pair
 // products.  u_i and v_i are formed index by index and consumed at once
 // rather than all fourteen of each first (fewer values live).
-template <int I>
-__device__ __forceinline__ void sum_wuv_comp_step(const DxPairs<double> &pu, const DxPairs<double> &pv, double &s,
-                                                  double &c)
+template <int I> __device__ __forceinline__ void wuv_acc(double uh, double ul, double vh, double vl, double &s, double &c)
 {
     constexpr double w = kW[I];
-    double uh, ul, vh, vl, p, pe;
-    dx_comp_r<I>(pu, uh, ul);
-    dx_comp_r<I>(pv, vh, vl);
+    double p, pe;
     two_prod(uh, vh, p, pe);
     const double corr = fma_(uh, vl, fma_(ul, vh, pe));
     if constexpr (I == 0) {
@@ -450,8 +492,27 @@ __device__ __forceinline__ void sum_wuv_comp_step(const DxPairs<double> &pu, con
         c = c + (te + fma_(w, corr, wpe));
         s = t;
     }
-    if constexpr (I < 13)
-        sum_wuv_comp_step<I + 1>(pu, pv, s, c);
+}
+
+template <int I>
+__device__ __forceinline__ void sum_wuv_comp_step(const DxPairs<double> &pu, const DxPairs<double> &pv, double &s,
+                                                  double &c)
+{
+    if constexpr (I == 7 || I == 9 || I == 11) {
+        double uh0, ul0, uh1, ul1, vh0, vl0, vh1, vl1;
+        dx_comp_r2<I>(pu, uh0, ul0, uh1, ul1);
+        dx_comp_r2<I>(pv, vh0, vl0, vh1, vl1);
+        wuv_acc<I>(uh0, ul0, vh0, vl0, s, c);
+        wuv_acc<I + 1>(uh1, ul1, vh1, vl1, s, c);
+        sum_wuv_comp_step<I + 2>(pu, pv, s, c);
+    } else {
+        double uh, ul, vh, vl;
+        dx_comp_r<I>(pu, uh, ul);
+        dx_comp_r<I>(pv, vh, vl);
+        wuv_acc<I>(uh, ul, vh, vl, s, c);
+        if constexpr (I < 13)
+            sum_wuv_comp_step<I + 1>(pu, pv, s, c);
+    }
 }
 
 __device__ __forceinline__ double sum_wuv_comp(const DxPairs<double> &pu, const DxPairs<double> &pv)
