@@ -505,13 +505,21 @@ __device__ __forceinline__ void sum_wuv_comp_step(const DxPairs<double> &pu, con
         wuv_acc<I>(uh0, ul0, vh0, vl0, s, c);
         wuv_acc<I + 1>(uh1, ul1, vh1, vl1, s, c);
         sum_wuv_comp_step<I + 2>(pu, pv, s, c);
+    } else if constexpr (I == 0 || I == 13) {
+        // r1 changes sign and r14 is unchanged under A -> A^T (the same
+        // products, commuted), so v1 = -u1 and v14 = u14
+        double uh, ul;
+        dx_comp_r<I>(pu, uh, ul);
+        const double sg = I == 0 ? -1.0 : 1.0;
+        wuv_acc<I>(uh, ul, sg * uh, sg * ul, s, c);
+        if constexpr (I < 13)
+            sum_wuv_comp_step<I + 1>(pu, pv, s, c);
     } else {
         double uh, ul, vh, vl;
         dx_comp_r<I>(pu, uh, ul);
         dx_comp_r<I>(pv, vh, vl);
         wuv_acc<I>(uh, ul, vh, vl, s, c);
-        if constexpr (I < 13)
-            sum_wuv_comp_step<I + 1>(pu, pv, s, c);
+        sum_wuv_comp_step<I + 1>(pu, pv, s, c);
     }
 }
 
