@@ -39,6 +39,7 @@ BYTES = {
     "bwd_general_f64": 9 * 8 + 3 * 8 + 9 * 8,
     "bwd_general_f32": 9 * 4 + 3 * 4 + 9 * 4,
     "step_general_f32": (9 * 4 + 3 * 4) + (9 * 4 + 3 * 4 + 9 * 4),
+    "step_general_f64": (9 * 8 + 3 * 8) + (9 * 8 + 3 * 8 + 9 * 8),
     "mohr_coulomb_symmetric_f64": 6 * 8 + 8 + 6 * 8,
     "eigenprojectors_general_f64": 9 * 8 + 27 * 8,
     "matrix_function_general_f64": 9 * 8 + 9 * 8,
@@ -326,6 +327,10 @@ def main():
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a, "general", acc_v, "soa", out=lam), "f64")
             variant(f"config5 bwd general f64 {acc_v}", "bwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals_backward(a, g, "general", acc_v, out=grad), "f64")
+        # the step with error-free products (within 8x the bounds at every kappa)
+        variant("config5 step f64 (compensated forward + adjoint)", "step_general_f64", N_MAIN,
+                lambda: (eig3.eig3_eigvals(a, "general", "compensated", "soa", out=lam),
+                         eig3.eig3_eigvals_backward(a, g, "general", "compensated", out=grad)), "f64")
         # eigenprojectors E_1..E_3 (27 outputs per matrix, write-heavy)
         eproj = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(27)]
         variant("config5 eigenprojectors general f64 fma", "eigenprojectors_general_f64", N_MAIN,
