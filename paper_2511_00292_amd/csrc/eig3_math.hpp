@@ -1244,6 +1244,48 @@ template <int Fn> __device__ __forceinline__ double divided_difference(double y,
         return 1.0 / (fx + fy);
 }
 
+// f at three ascending nodes y0 <= y1 <= y2, given with their gaps g01 = y1 - y0
+// and g12 = y2 - y1 (>= 0, free of cancellation), and the three first divided
+// differences.  For exp and log the later values follow from the first and
+// the increments the divided differences need anyway: e^y1 = e^y0 (1 +
+// expm1(g01)), log y1 = log y0 + log1p(g01 / y0), and over the whole spread
+// expm1(g01 + g12) = a + b + a b, log1p = a + b (sums of nonnegative terms),
+// so one exp or log and two expm1 or log1p serve all six values.
+struct Chain {
+    double f0, f1, f2;    // f(y0), f(y1), f(y2)
+    double d01, d12, d02; // f[y0, y1], f[y1, y2], f[y0, y2]
+};
+template <int Fn> __device__ __forceinline__ Chain node_chain(double y0, double y1, double y2, double g01, double g12)
+{
+    Chain c;
+    const double g02 = g01 + g12;
+    if constexpr (Fn == EIG3_EXP) {
+        const double a = expm1(g01), b = expm1(g12);
+        c.f0 = exp(y0);
+        c.f1 = fma_(c.f0, a, c.f0);
+        c.f2 = fma_(c.f1, b, c.f1);
+        c.d01 = g01 == 0.0 ? c.f0 : c.f0 * (a / g01);
+        c.d12 = g12 == 0.0 ? c.f1 : c.f1 * (b / g12);
+        c.d02 = g02 == 0.0 ? c.f0 : c.f0 * (fma_(a, b, a + b) / g02);
+    } else if constexpr (Fn == EIG3_LOG) {
+        const double a = log1p(g01 / y0), b = log1p(g12 / y1);
+        c.f0 = log(y0);
+        c.f1 = c.f0 + a;
+        c.f2 = c.f1 + b;
+        c.d01 = g01 == 0.0 ? 1.0 / y0 : a / g01;
+        c.d12 = g12 == 0.0 ? 1.0 / y1 : b / g12;
+        c.d02 = g02 == 0.0 ? 1.0 / y0 : (a + b) / g02;
+    } else {
+        c.f0 = sqrt(y0);
+        c.f1 = sqrt(y1);
+        c.f2 = sqrt(y2);
+        c.d01 = 1.0 / (c.f0 + c.f1);
+        c.d12 = 1.0 / (c.f1 + c.f2);
+        c.d02 = 1.0 / (c.f0 + c.f2);
+    }
+    return c;
+}
+
 // f''(y) / 2 from y and fy = f(y)
 template <int Fn> __device__ __forceinline__ double half_second_derivative(double y, double fy)
 {
@@ -1273,9 +1315,8 @@ template <int Fn> __device__ __forceinline__ void matrix_function_general(const 
     mu_from_trig(t, m1, m2, m3);
     const double l1 = t.mean + m1, l2 = t.mean + m2;
     const Gaps gp = gaps_from_trig(t);
-    const double f1 = scalar_function<Fn>(l1), f2 = scalar_function<Fn>(l2);
-    const double d12 = divided_difference<Fn>(l1, f2, f1, gp.e12);
-    const double d23 = divided_difference<Fn>(l2, scalar_function<Fn>(t.mean + m3), f2, gp.e23);
+    const Chain ch = node_chain<Fn>(l1, l2, t.mean + m3, gp.e12, gp.e23);
+    const double f1 = ch.f0, d12 = ch.d01, d23 = ch.d12;
     // all three equal: the confluent limit f''(lambda) / 2 (P1 P2 is the square
     // of the nilpotent part, zero unless A is a single Jordan block)
     const double d123 = gp.e13 == 0.0 ? half_second_derivative<Fn>(l1, f1) : (d23 - d12) / gp.e13;
@@ -1355,16 +1396,17 @@ __device__ __forceinline__ void matrix_function_backward_general(const Gen &A, c
     mu_from_trig(t, m1, m2, m3);
     const Gaps gp = gaps_from_trig(t);
     const double z0 = t.mean + m1, z1 = t.mean + m3, z2 = t.mean + m2;
-    const double f0 = scalar_function<Fn>(z0), f1 = scalar_function<Fn>(z1), f2 = scalar_function<Fn>(z2);
+    const Chain ch = node_chain<Fn>(z0, z2, z1, gp.e12, gp.e23); // ascending: z0, z2, z1
+    const double f0 = ch.f0, f1 = ch.f2, f2 = ch.f1;
     const double spread = gp.e13;
     const bool iso = spread == 0.0;
     constexpr double kTau = 0x1p-26;
     const bool low = gp.e12 <= kTau * spread;  // z2 merges with z0
     const bool high = gp.e23 <= kTau * spread; // z2 merges with z1
     // first order (cancellation-free formulas, exact zero gaps included)
-    const double d01 = divided_difference<Fn>(z0, f1, f0, spread);     // f[z0, z1]
-    const double d02 = divided_difference<Fn>(z0, f2, f0, gp.e12);     // f[z0, z2]
-    const double d12 = divided_difference<Fn>(z2, f1, f2, gp.e23);     // f[z2, z1]
+    const double d01 = ch.d02; // f[z0, z1]
+    const double d02 = ch.d01; // f[z0, z2]
+    const double d12 = ch.d12; // f[z2, z1]
     const double c00 = taylor_coefficient<Fn>(1, z0, f0);              // f[z0, z0]
     const double c11 = taylor_coefficient<Fn>(1, z1, f1);              // f[z1, z1]
     const double c22 = taylor_coefficient<Fn>(1, z2, f2);              // f[z2, z2]
