@@ -349,7 +349,12 @@ def main():
         lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)
         variant("config5 fwd general f64 fma aos", "fwd_general_f64", N_MAIN,
                 lambda: eig3.eig3_eigvals(a_aos, "general", "fma", "aos", out=lam_aos), "f64")
-        del a_aos, lam_aos
+        # the adjoint as the autograd Function calls it: g (n, 3), dL/dA (n, 3, 3)
+        g_aos = torch.stack(g, dim=1).contiguous()
+        grad_aos = torch.empty_like(a_aos)
+        variant("config5 bwd general f64 fma aos", "bwd_general_f64", N_MAIN,
+                lambda: eig3.eig3_eigvals_backward(a_aos, g_aos, "general", "fma", out=grad_aos), "f64")
+        del a_aos, lam_aos, g_aos, grad_aos
         # the same workload stored in binary32: forward in both evaluations,
         # the adjoint (binary64 arithmetic, rounded once), and the whole step
         a32 = [t.float() for t in a]
