@@ -25,8 +25,8 @@ from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EI
 
 __all__ = [
     "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors",
-    "eig3_matrix_function", "eig3_matrix_function_backward", "eigvals", "matrix_function",
-    "Eig3Eigvals", "Eig3MatrixFunction",
+    "eig3_matrix_function", "eig3_matrix_function_backward", "eigvals", "eigvals_symmetric", "matrix_function",
+    "Eig3Eigvals", "Eig3EigvalsSymmetric", "Eig3MatrixFunction",
     "ENTRIES", "Eig3Error", "version",
 ]
 
@@ -316,3 +316,35 @@ class Eig3Eigvals(torch.autograd.Function):
 def eigvals(a: torch.Tensor, accuracy: str = "fma") -> torch.Tensor:
     """Ascending eigenvalues of a (..., 3, 3) float64 device tensor, differentiable."""
     return Eig3Eigvals.apply(a, accuracy)
+
+
+class Eig3EigvalsSymmetric(torch.autograd.Function):
+    """lambda = eigvals(S) for symmetric matrices stored as (..., 6) tensors,
+    entries (A00, A11, A22, A01, A02, A12), read by the kernels as they are;
+    the backward is the symmetric ``eig3_eigvals_backward``: the gradient with
+    respect to the six stored entries (an off-diagonal entry counts both of its
+    positions)."""
+
+    @staticmethod
+    def forward(ctx, s: torch.Tensor, accuracy: str = "fma"):
+        shape = s.shape
+        if shape[-1] != 6:
+            raise ValueError("expected (..., 6): A00 A11 A22 A01 A02 A12")
+        sc = s.contiguous()
+        lam = eig3_eigvals(sc.reshape(-1, 6), "symmetric", accuracy, "aos")
+        ctx.save_for_backward(sc)
+        ctx.accuracy = accuracy
+        return lam.reshape(*shape[:-1], 3)
+
+    @staticmethod
+    def backward(ctx, glam: torch.Tensor):
+        (sc,) = ctx.saved_tensors
+        g = glam.contiguous().reshape(-1, 3)
+        grad = eig3_eigvals_backward(sc.reshape(-1, 6), g, "symmetric", ctx.accuracy)
+        return grad.reshape(sc.shape), None
+
+
+def eigvals_symmetric(s: torch.Tensor, accuracy: str = "fma") -> torch.Tensor:
+    """Ascending eigenvalues of symmetric matrices stored as a (..., 6) device
+    tensor (A00 A11 A22 A01 A02 A12), float64 or float32, differentiable."""
+    return Eig3EigvalsSymmetric.apply(s, accuracy)
