@@ -58,7 +58,7 @@ extern "C" {
 typedef enum eig3_status {
     EIG3_OK = 0,
     EIG3_EINVAL = -1,       /* invalid argument; nothing was launched */
-    EIG3_EUNSUPPORTED = -2, /* valid combination that this build does not provide */
+    EIG3_EUNSUPPORTED = -2, /* valid combination that the library does not provide */
     EIG3_ELAUNCH = -3       /* the HIP runtime reported a launch error */
 } eig3_status;
 

@@ -839,7 +839,7 @@ const char *eig3_status_string(int status)
     case EIG3_EINVAL:
         return "EIG3_EINVAL: invalid argument";
     case EIG3_EUNSUPPORTED:
-        return "EIG3_EUNSUPPORTED: combination not provided by this build";
+        return "EIG3_EUNSUPPORTED: combination not provided by the library";
     case EIG3_ELAUNCH:
         return "EIG3_ELAUNCH: kernel launch failed";
     default:
