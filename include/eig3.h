@@ -29,6 +29,14 @@
  *    and Delta < 0 (possible after rounding for nonsymmetric input) are
  *    clamped to 0 before the square roots, so a complex pair a +- ib comes
  *    back as a double real value near a.  NaN input propagates to NaN output.
+ *  - Range: binary64 batches are evaluated on A scaled by the power of two
+ *    that brings its largest entry into [1/2, 1) (exact; the results scale
+ *    back exactly), so eigenvalues, their adjoint, the eigenprojectors and
+ *    the Mohr-Coulomb function hold over the whole binary64 range;
+ *    eig3_invariants returns the invariants themselves, which overflow
+ *    (Delta ~ |A|^6) beyond about 2^170 and underflow below about 2^-170,
+ *    and the functions of matrices work on A as it is.  The naive
+ *    comparators are evaluated as printed, without scaling.
  *  - Eigenvalues are returned in ascending order lambda_1 <= lambda_2 <=
  *    lambda_3 (Sec. "Introduction and motivation", ordering property).
  *  - Accuracy: with unit roundoff eps (2^-53 binary64, 2^-24 binary32),

@@ -396,6 +396,34 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
     }
 }
 
+// Binary64 batches are evaluated on A 2^-e, 2^e the binade of A's largest
+// entry (max |A_ij| in [1/2, 1) after scaling).  I1, J2, J3 and Delta are
+// homogeneous of degree 1, 2, 3, 6 in the entries, so the scaled evaluation
+// is the unscaled one times exact powers of two (bitwise the same results
+// where nothing under- or overflows), while Delta ~ |A|^6 stays inside the
+// binary64 range for every finite input (unscaled it over- or underflows
+// beyond about 2^+-160).  Eigenvalues and the Mohr-Coulomb stresses scale
+// back by 2^e; the eigenvalue gradient and the eigenprojectors do not change
+// with the scale.  (Binary32 entries widened to binary64 stay in range
+// without it; the paper's naive comparators are left as printed.)
+template <int S> __device__ __forceinline__ int prescale(Mat<double, S> &m)
+{
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < Mat<double, S>::K; ++k)
+        mx = fmax(mx, fabs(m.a[k]));
+    const int e = __builtin_amdgcn_frexp_exp(mx); // 0 for 0, Inf and NaN: no scaling
+#pragma unroll
+    for (int k = 0; k < Mat<double, S>::K; ++k)
+        m.a[k] = ldexp(m.a[k], -e);
+    return e;
+}
+
+template <class T, int Acc> constexpr bool scaled_path()
+{
+    return sizeof(T) == 8 && (Acc == EIG3_FMA || Acc == EIG3_COMPENSATED);
+}
+
 // ------------------------------------------------------------------ kernels
 template <class T, int S, int L, int Acc>
 EIG3_KERNEL void k_invariants(int64_t n, In9<T> in, OutK<T, 4> out)
@@ -412,11 +440,18 @@ EIG3_KERNEL void k_invariants(int64_t n, In9<T> in, OutK<T, 4> out)
 template <class T, int S, int L, int OL, int Acc>
 EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
 {
-    for_each_matrix<T, S, L, 3, OL>(n, in, out, [&](const Span &, const Mat<T, S> &m, double (&o)[3]) {
-        const auto v = invariants_of<S, Acc>(m);
-        if constexpr (sizeof(T) == 8) {
-            eigvals_from_invariants(v, o[0], o[1], o[2]);
+    for_each_matrix<T, S, L, 3, OL>(n, in, out, [&](const Span &, const Mat<T, S> &mt, double (&o)[3]) {
+        if constexpr (scaled_path<T, Acc>()) {
+            Mat<double, S> m = mt;
+            const int e = prescale(m);
+            eigvals_from_invariants(invariants_of<S, Acc>(m), o[0], o[1], o[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                o[k] = ldexp(o[k], e);
+        } else if constexpr (sizeof(T) == 8) {
+            eigvals_from_invariants(invariants_of<S, Acc>(mt), o[0], o[1], o[2]);
         } else {
+            const auto v = invariants_of<S, Acc>(mt);
             float l1, l2, l3;
             eigvals_f32_from_invariants(v, l1, l2, l3);
             o[0] = l1;
@@ -541,7 +576,9 @@ EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, OutK<T, Mat<T, S>::K>
             g2 = double(span_ld(g.p[0], sp, 3, 1));
             g3 = double(span_ld(g.p[0], sp, 3, 2));
         }
-        const Mat<double, S> m = widen(mt);
+        Mat<double, S> m = widen(mt);
+        if constexpr (scaled_path<T, Acc>())
+            prescale(m); // the gradient does not change with the scale
         const Inv v = invariants_of<S, Acc>(m);
         const Coef c = backward_coefficients(v, g1, g2, g3);
         double gr[9];
@@ -562,11 +599,14 @@ EIG3_KERNEL void k_mohr_coulomb(int64_t n, In9<T> in, double cf, double K, T *__
     constexpr int KO = Grad ? Mat<T, S>::K : 1;
     constexpr int OL = Grad ? L : EIG3_SOA;
     for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](const Span &sp, const Mat<T, S> &mt, double (&o)[KO]) {
-        const Mat<double, S> m = widen(mt);
+        Mat<double, S> m = widen(mt);
+        int e = 0;
+        if constexpr (scaled_path<T, Acc>())
+            e = prescale(m);
         const Inv v = invariants_of<S, Acc>(m);
         // the gradient kernel carries many pointers: its coefficients are
         // immediates rather than SGPR-resident constants
-        const MohrCoulomb mc = mohr_coulomb<!Grad>(v, cf, K);
+        const MohrCoulomb mc = mohr_coulomb<!Grad>(v, cf, K, e);
         if constexpr (Grad) {
             span_st(T(mc.f), f, sp);
             const Coef c = backward_coefficients(mc.t, mc.g1, 0.0, mc.g3);
@@ -589,7 +629,9 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
     constexpr int KS = Mat<T, S>::K;
     constexpr int KO = 3 * KS;
     for_each_matrix<T, S, L, KO, OL>(n, in, out, [&](const Span &, const Mat<T, S> &mt, double (&o)[KO]) {
-        const Mat<double, S> m = widen(mt);
+        Mat<double, S> m = widen(mt);
+        if constexpr (scaled_path<T, Acc>())
+            prescale(m); // the projectors do not change with the scale
         const Inv v = invariants_of<S, Acc>(m);
         const Trig t = trig_from_invariants<false>(v);
         double E[27];

@@ -1164,7 +1164,9 @@ struct MohrCoulomb {
     Trig t;        // the triple-angle quantities, reused by the gradient
 };
 
-template <bool Table = true> __device__ __forceinline__ MohrCoulomb mohr_coulomb(const Inv &v, double cf, double K)
+// (v may be the invariants of sigma 2^-e: the stresses scale back by 2^e)
+template <bool Table = true>
+__device__ __forceinline__ MohrCoulomb mohr_coulomb(const Inv &v, double cf, double K, int e = 0)
 {
     const Trig t = trig_from_invariants<Table>(v);
     double m1, m2, m3;
@@ -1173,7 +1175,7 @@ template <bool Table = true> __device__ __forceinline__ MohrCoulomb mohr_coulomb
     const double p12 = (s2 - s1) + K * (s1 + s2);
     const double p13 = (s3 - s1) + K * (s1 + s3);
     const double p23 = (s3 - s2) + K * (s2 + s3);
-    const double pm = fmax(fmax(p12, p13), p23);
+    const double pm = ldexp(fmax(fmax(p12, p13), p23), e);
     MohrCoulomb r;
     r.f = fma_(cf, pm, -1.0);
     r.g1 = cf * (K - 1.0);

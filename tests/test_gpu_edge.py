@@ -156,3 +156,45 @@ def test_output_tensors_validated(eig3):
     # well-formed outputs still work
     lam = eig3.eig3_eigvals(a, out=torch.empty((100, 3), dtype=f64, device=d))
     assert torch.all(lam == 0)
+
+
+@pytest.mark.parametrize("acc", ACCS)
+@pytest.mark.parametrize("structure", ["general", "symmetric"])
+def test_binary64_full_range(eig3, acc, structure):
+    """Binary64 batches are evaluated on A scaled by a power of two, so
+    eigenvalues of 2^k A are exactly 2^k times those of A, and the adjoint and
+    the eigenprojectors of 2^k A are those of A, over the whole binary64
+    range (k = -900 .. 1000; without the scaling Delta ~ |A|^6 over- or
+    underflows beyond about 2^+-160); sampled matrices at 2^-900 meet the
+    bound against the exact oracle (at 2^1000 the oracle's own bound scales
+    exceed binary64; there the exact relation to the scale-1 results is the
+    check)."""
+    import torch
+    rng = np.random.default_rng(77)
+    mats = []
+    for _ in range(300):
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        lam = np.sort(rng.uniform(-1.0, 1.0, 3))
+        m = q @ np.diag(lam) @ q.T
+        mats.append(m.ravel() if structure == "general" else
+                    [m[0, 0], m[1, 1], m[2, 2], m[0, 1], m[0, 2], m[1, 2]])
+    a = np.array(mats)
+    g = rng.standard_normal((len(a), 3))
+    dev = torch.device("cuda:0")
+    at = torch.tensor(a, device=dev)
+    gt = torch.tensor(g, device=dev)
+    lam0 = eig3.eig3_eigvals(at, structure, acc, "aos")
+    grad0 = eig3.eig3_eigvals_backward(at, gt, structure, acc)
+    proj0 = eig3.eig3_eigenprojectors(at, structure, acc, "aos")
+    for k in (-900, -300, 300, 1000):
+        f = math.ldexp(1.0, k)  # exact power of two (a device pow need not be)
+        ak = at * f
+        lam = eig3.eig3_eigvals(ak, structure, acc, "aos")
+        assert torch.equal(lam, lam0 * f), k
+        assert torch.equal(eig3.eig3_eigvals_backward(ak, gt, structure, acc), grad0), k
+        assert torch.equal(eig3.eig3_eigenprojectors(ak, structure, acc, "aos"), proj0), k
+        if k == -900:
+            full = w.symmetric_to_general(ak.cpu().numpy()) if structure == "symmetric" else ak.cpu().numpy()
+            t = Truth(full[::10], np.ones(len(full[::10])))
+            check(lam_errors(t, lam.cpu().numpy()[::10]), t.bound_lam(), what=f"2^{k} {structure} {acc}")
