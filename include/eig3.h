@@ -179,7 +179,8 @@ int eig3_eigvals_backward(const eig3_matrices *A, int32_t g_layout, const void *
  *   components of the (symmetric) tensor derivative; the derivative with
  *   respect to a stored off-diagonal entry is twice its component.
  *   +-Inf/NaN at the corners of the yield surface (s_1 = s_2 or s_2 = s_3).
- * s_yc > 0 and m > 0 (finite), else EIG3_EINVAL.  Arithmetic in binary64.
+ * 0 < s_yc <= 1e300 and 0 < m <= 1e300, else EIG3_EINVAL.  Arithmetic in
+ * binary64.
  */
 int eig3_mohr_coulomb(const eig3_matrices *sigma, double s_yc, double m, void *f, void *const dfds[9],
                       hipStream_t stream);

@@ -111,3 +111,26 @@ def test_invalid_parameters(eig3):
     for syc, m in ((0.0, 10.0), (100.0, -1.0), (float("nan"), 2.0)):
         with pytest.raises(eig3.Eig3Error):
             eig3.eig3_mohr_coulomb(s, syc, m, "symmetric")
+
+
+@pytest.mark.parametrize("acc", ["fma", "compensated"])
+def test_binary64_scale_invariance(eig3, acc):
+    """Binary64 stresses are evaluated on sigma scaled by a power of two:
+    with sigma and S_yc both scaled by 2^k, f is bitwise unchanged and
+    df/dsigma scales by exactly 2^-k, from 2^-900 to 2^900 (where the
+    unscaled discriminant would over- or underflow; S_yc itself is limited
+    to 1e300)."""
+    import math
+
+    import torch
+    g = _golden()
+    syc, m = g["S_yc"], g["S_yc"] / g["S_yt"]
+    rng = np.random.default_rng(81)
+    s = rng.standard_normal((500, 6)) * 50.0
+    st = torch.tensor(s, device="cuda:0")
+    f0, d0 = eig3.eig3_mohr_coulomb(st, syc, m, "symmetric", acc)
+    for k in (-900, -300, 300, 900):
+        fac = math.ldexp(1.0, k)  # exact power of two
+        f, d = eig3.eig3_mohr_coulomb(st * fac, syc * fac, m, "symmetric", acc)
+        assert torch.equal(f, f0), k
+        assert torch.equal(d, d0 * math.ldexp(1.0, -k)), k
