@@ -26,7 +26,8 @@ from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EI
 __all__ = [
     "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors",
     "eig3_matrix_function", "eig3_matrix_function_backward", "eigvals", "eigvals_symmetric", "matrix_function",
-    "Eig3Eigvals", "Eig3EigvalsSymmetric", "Eig3MatrixFunction",
+    "matrix_function_symmetric", "Eig3Eigvals", "Eig3EigvalsSymmetric", "Eig3MatrixFunction",
+    "Eig3MatrixFunctionSymmetric",
     "ENTRIES", "Eig3Error", "version",
 ]
 
@@ -263,9 +264,9 @@ def eig3_matrix_function_backward(a: Batch, g: Batch, fn: str = "exp", structure
 
 
 class Eig3MatrixFunction(torch.autograd.Function):
-    """F = f(A) for A of shape (..., 3, 3) (general, distinct eigenvalues),
-    f in ('exp', 'log', 'sqrt'), with eig3_matrix_function_backward as its
-    backward."""
+    """F = f(A) for A of shape (..., 3, 3) (general; coalescing and repeated
+    eigenvalues included), f in ('exp', 'log', 'sqrt'), with
+    eig3_matrix_function_backward as its backward."""
 
     @staticmethod
     def forward(ctx, a: torch.Tensor, fn: str = "exp", accuracy: str = "fma"):
@@ -288,6 +289,37 @@ class Eig3MatrixFunction(torch.autograd.Function):
 def matrix_function(a: torch.Tensor, fn: str = "exp", accuracy: str = "fma") -> torch.Tensor:
     """f(A) of a (..., 3, 3) device tensor, differentiable."""
     return Eig3MatrixFunction.apply(a, fn, accuracy)
+
+
+class Eig3MatrixFunctionSymmetric(torch.autograd.Function):
+    """F = f(S) for symmetric matrices stored as (..., 6) tensors (A00 A11 A22
+    A01 A02 A12), F in the same six-component storage; the kernels read and
+    write that storage as it is.  The backward is the symmetric
+    eig3_matrix_function_backward: from dL/d(the six components of F) to
+    dL/d(the six stored entries of S)."""
+
+    @staticmethod
+    def forward(ctx, s: torch.Tensor, fn: str = "exp", accuracy: str = "fma"):
+        if s.shape[-1] != 6:
+            raise ValueError("expected (..., 6): A00 A11 A22 A01 A02 A12")
+        sc = s.contiguous()
+        f = eig3_matrix_function(sc.reshape(-1, 6), fn, "symmetric", accuracy)
+        ctx.save_for_backward(sc)
+        ctx.fn, ctx.accuracy = fn, accuracy
+        return f.reshape(sc.shape)
+
+    @staticmethod
+    def backward(ctx, gf: torch.Tensor):
+        (sc,) = ctx.saved_tensors
+        grad = eig3_matrix_function_backward(sc.reshape(-1, 6), gf.contiguous().reshape(-1, 6), ctx.fn, "symmetric",
+                                             ctx.accuracy)
+        return grad.reshape(sc.shape), None, None
+
+
+def matrix_function_symmetric(s: torch.Tensor, fn: str = "exp", accuracy: str = "fma") -> torch.Tensor:
+    """f(S) of symmetric matrices stored as a (..., 6) device tensor
+    (A00 A11 A22 A01 A02 A12), in the same storage, differentiable."""
+    return Eig3MatrixFunctionSymmetric.apply(s, fn, accuracy)
 
 
 class Eig3Eigvals(torch.autograd.Function):

@@ -298,3 +298,29 @@ def test_autograd_isotropic_log(eig3):
     for m in range(4, 8):
         ref = np.array(exact.matrix_function_vjp(ad[m], "log", wgt[m].cpu().numpy().ravel()))
         assert _rel(grad[m].ravel(), ref) <= 1e-13, m
+
+
+@pytest.mark.parametrize("fn", ["exp", "log", "sqrt"])
+def test_autograd_symmetric_storage(eig3, fn):
+    """eig3.matrix_function_symmetric on (..., 6) storage against
+    eig3.matrix_function on the full matrices built from the same six entries
+    by differentiable torch ops, with the loss taken on the six components of
+    F: same values, and the same gradient with respect to the stored entries."""
+    import torch
+    a = _spd(400, 106)
+    s = np.stack([a[:, 0], a[:, 4], a[:, 8], a[:, 1], a[:, 2], a[:, 5]], axis=1).reshape(4, 100, 6)
+    wgt = torch.tensor(np.random.default_rng(107).standard_normal((4, 100, 6)), device="cuda:0")
+    s1 = torch.tensor(s, device="cuda:0").requires_grad_(True)
+    f1 = eig3.matrix_function_symmetric(s1, fn)
+    (f1 * wgt).sum().backward()
+    s2 = torch.tensor(s, device="cuda:0").requires_grad_(True)
+    rows = [torch.stack([s2[..., 0], s2[..., 3], s2[..., 4]], -1),
+            torch.stack([s2[..., 3], s2[..., 1], s2[..., 5]], -1),
+            torch.stack([s2[..., 4], s2[..., 5], s2[..., 2]], -1)]
+    full = eig3.matrix_function(torch.stack(rows, -2), fn)
+    f2 = torch.stack([full[..., 0, 0], full[..., 1, 1], full[..., 2, 2], full[..., 0, 1], full[..., 0, 2],
+                      full[..., 1, 2]], -1)
+    (f2 * wgt).sum().backward()
+    assert f1.shape == s1.shape and s1.grad.shape == s1.shape
+    assert torch.all((f1 - f2).detach().abs() <= 1e-13 * f2.detach().abs().amax(-1, keepdim=True))
+    assert torch.all((s1.grad - s2.grad).abs() <= 1e-12 * s2.grad.abs().amax(-1, keepdim=True))
