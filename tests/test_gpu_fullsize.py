@@ -132,3 +132,108 @@ def test_config5_full_2p24_step(eig3, plain_oracle):
     assert np.isfinite(r).all() and np.isfinite(rc).all()
     assert r.max() <= 2.0 * rp.max() + 1e-8, (r.max(), rp.max())
     assert rc.max() <= min(r.max(), 2.0 * rp.max() + 1e-8), (rc.max(), r.max(), rp.max())
+
+
+def test_config5_full_2p24_matrix_exp_and_projectors(eig3):
+    """The matrix exponential, its adjoint and the eigenprojectors at the
+    benchmark's size and launch shape (2^24 general binary64 matrices,
+    structure of arrays).  Sampled outputs against the exact oracle
+    (80-digit eigenprojectors and f); on every output, d tr(exp A)/dA =
+    exp(A)^T (the adjoint with G = I against the forward) and sum_k E_k = I."""
+    import torch
+    from oracle import exact
+    n = 1 << 24
+    c = w.config5(n, seed=5)
+    a_dev = upload(c["a"], "soa")
+    f = torch.stack(eig3.eig3_matrix_function(a_dev, "exp", "general", "fma"), 1)
+    eye = [torch.full((n,), float(k in (0, 4, 8)), dtype=torch.float64, device=f.device) for k in range(9)]
+    g_i = torch.stack(eig3.eig3_matrix_function_backward(a_dev, tuple(eye), "exp", "general", "fma"), 1)
+    del eye
+    rng = np.random.default_rng(55)
+    g_r = rng.standard_normal((n, 9))
+    g_r_dev = upload(g_r, "soa")
+    grad = torch.stack(eig3.eig3_matrix_function_backward(a_dev, g_r_dev, "exp", "general", "fma"), 1)
+    del g_r_dev
+    f_t = f.reshape(n, 3, 3).transpose(1, 2).reshape(n, 9)
+    scale = f.abs().amax(1)
+    r = ((g_i - f_t).abs().amax(1) / scale).max().item()
+    assert torch.isfinite(f).all() and torch.isfinite(g_i).all() and torch.isfinite(grad).all()
+    assert r <= 2e-11, r
+    del g_i, f_t
+    e = torch.stack(eig3.eig3_eigenprojectors(a_dev, "general", "fma", "soa"), 1)
+    del a_dev
+    eye9 = torch.tensor([1.0, 0, 0, 0, 1, 0, 0, 0, 1], dtype=torch.float64, device=e.device)
+    # each E_k carries the error of the eigenvalues (kappa eps |A|, kappa <= 100)
+    # divided by gaps down to 1e-3: about 1e-11 of max |E|
+    resid = (e[:, 0:9] + e[:, 9:18] + e[:, 18:27] - eye9).abs().amax(1) / e.abs().amax(1)
+    assert resid.max().item() <= 1e-10, resid.max().item()
+    idx = np.sort(rng.choice(n, 48, replace=False))
+    it = torch.from_numpy(idx).to(e.device)
+    f_s, grad_s, e_s = (x.index_select(0, it).cpu().numpy() for x in (f, grad, e))
+    for j, m in enumerate(idx):
+        ref = np.array(exact.matrix_function(c["a"][m], "exp"))
+        assert np.abs(f_s[j] - ref).max() <= 1e-12 * np.abs(ref).max(), int(m)
+        ref = np.array(exact.matrix_function_vjp(c["a"][m], "exp", g_r[m]))
+        assert np.abs(grad_s[j] - ref).max() <= 1e-11 * np.abs(ref).max(), int(m)
+        ref = np.array(exact.eigenprojectors(c["a"][m]))
+        assert np.abs(e_s[j] - ref).max() <= 1e-8 * np.abs(ref).max(), int(m)
+
+
+def test_config3_full_2p27_mohr_coulomb(eig3):
+    """Mohr-Coulomb f and df/dsigma at the benchmark's size and launch shape
+    (2^27 symmetric binary64 stress tensors, S_yc = 100, m = 10).  Sampled
+    outputs against the exact oracle; on every output two identities of the
+    yield function f + 1 = c max_{i<j}(|s_i - s_j| + K(s_i + s_j)),
+    c = (m + 1)/(2 S_yc), K = (m - 1)/(m + 1): df/dsigma = c((K - 1) E_min +
+    (K + 1) E_max) has trace (m - 1)/S_yc, and f + 1 is homogeneous of degree
+    one in sigma, so sigma : df/dsigma = f + 1 (Euler).  Computed
+    eigenprojectors carry an error of eps |sigma| / gap, so both identities
+    are held to 16 eps times cond = 1 + |sigma| / gap (the gap from the
+    library's eigenvalues, which sizes the tolerance only); the Euler scale
+    also holds |f|, since f = -1 + (f + 1) is rounded near -1.  Measured
+    maxima on this batch: 3.0 (trace) and 2.9 (Euler) in those units."""
+    import torch
+    from oracle import exact
+    n = 1 << 27
+    syc, mm = 100.0, 10.0
+    s = w.config3(n)["s"]
+    s_dev = upload(s, "soa")
+    f, dfds = eig3.eig3_mohr_coulomb(s_dev, syc, mm, "symmetric", "fma")
+    g = torch.stack(dfds, 1)
+    del dfds
+    lam = torch.stack(eig3.eig3_eigvals(s_dev, "symmetric", "fma", "soa"), 1)
+    sd = torch.stack(s_dev, 1)
+    del s_dev
+    assert torch.isfinite(f).all() and torch.isfinite(g).all()
+    c = (mm + 1) / (2 * syc)
+    gap = torch.minimum(lam[:, 1] - lam[:, 0], lam[:, 2] - lam[:, 1])
+    nrm = torch.sqrt((sd[:, :3] ** 2).sum(1) + 2 * (sd[:, 3:] ** 2).sum(1))
+    cond = 1 + nrm / torch.clamp(gap, min=1e-300)
+    del lam, gap
+    tr = g[:, 0] + g[:, 1] + g[:, 2]
+    r_tr = ((tr - (mm - 1) / syc).abs() / (EPS64 * c * cond)).max().item()
+    assert r_tr <= 16, r_tr
+    prod = sd[:, :3] * g[:, :3]
+    off = 2 * sd[:, 3:] * g[:, 3:]
+    euler = prod.sum(1) + off.sum(1)
+    scale = prod.abs().sum(1) + off.abs().sum(1) + (f + 1).abs() + f.abs() + c * nrm * cond
+    r_eu = ((euler - (f + 1)).abs() / (EPS64 * scale)).max().item()
+    assert r_eu <= 16, r_eu
+    del sd, prod, off, euler, scale, cond, nrm
+    rng = np.random.default_rng(33)
+    idx = np.sort(rng.choice(n, 300, replace=False))
+    it = torch.from_numpy(idx).to(g.device)
+    f_s, g_s = f.index_select(0, it).cpu().numpy(), g.index_select(0, it).cpu().numpy()
+    a = w.symmetric_to_general(s[idx])
+    for j in range(len(idx)):
+        fe, ge = exact.mohr_coulomb(a[j], syc, mm)
+        nrm = np.linalg.norm(a[j])
+        assert abs(f_s[j] - fe) <= 8 * (mm + 1) / syc * nrm * EPS64 + 8 * EPS64, (int(idx[j]), f_s[j], fe)
+        lam = np.sort(np.real(exact.eigvals_float(a[j])))
+        gap = min(lam[1] - lam[0], lam[2] - lam[1]) / max(nrm, 1e-300)
+        if gap > 1e-6:
+            gs = np.array(ge).reshape(3, 3)
+            gs = 0.5 * (gs + gs.T)
+            ref = np.array([gs[0, 0], gs[1, 1], gs[2, 2], gs[0, 1], gs[0, 2], gs[1, 2]])
+            tol = 1e-9 * np.abs(ref).max() / min(gap * 1e3, 1.0)
+            assert np.abs(g_s[j] - ref).max() <= tol, (int(idx[j]), g_s[j], ref)
