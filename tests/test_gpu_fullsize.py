@@ -237,3 +237,47 @@ def test_config3_full_2p27_mohr_coulomb(eig3):
             ref = np.array([gs[0, 0], gs[1, 1], gs[2, 2], gs[0, 1], gs[0, 2], gs[1, 2]])
             tol = 1e-9 * np.abs(ref).max() / min(gap * 1e3, 1.0)
             assert np.abs(g_s[j] - ref).max() <= tol, (int(idx[j]), g_s[j], ref)
+
+
+@pytest.mark.parametrize("acc", ["fma", "compensated"])
+def test_config5_full_2p24_f32(eig3, acc):
+    """The benchmark's binary32 step at its size and launch shape: 2^24
+    general matrices of the differentiation batch stored in binary32,
+    structure of arrays (two matrices per lane in the forward).  Forward:
+    sampled outputs against the exact eigenvalues of the stored matrices
+    (G1 with eps = 2^-24), ascending order and the trace on every output.
+    Adjoint (binary64 arithmetic, rounded once): sampled outputs against the
+    exact gradient at the stored matrices within 4 eps, and with g = (1, 1, 1)
+    the gradient sum_k E_k^T = I on every output within 4 eps."""
+    import torch
+    from oracle import exact
+    from accuracy import EPS32
+    n = 1 << 24
+    c = w.config5(n, seed=6)
+    a32 = c["a"].astype(np.float32)
+    g32 = c["g"].astype(np.float32)
+    a_dev = upload(a32, "soa")
+    lam = download_lam(eig3.eig3_eigvals(a_dev, "general", acc, "soa"))
+    assert np.isfinite(lam).all() and np.all(np.diff(lam, axis=1) >= 0)
+    a64 = a32.astype(np.float64)
+    tr = a64[:, 0] + a64[:, 4] + a64[:, 8]
+    nrm = np.sqrt((a64 * a64).sum(1))
+    assert np.all(np.abs(lam.astype(np.float64).sum(1) - tr) <= 8 * 3 * (c["kappa"] + 1) * nrm * EPS32)
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(n, 1200, replace=False))
+    t = Truth(a64[idx], c["kappa"][idx])
+    check(lam_errors(t, lam[idx].astype(np.float64)), t.bound_lam(EPS32), what=f"config5 2^24 f32 {acc} (G1)")
+    if acc != "fma":
+        return
+    g_dev = upload(g32, "soa")
+    grad = torch.stack(eig3.eig3_eigvals_backward(a_dev, g_dev, "general", "fma"), 1)
+    ones = tuple(torch.ones(n, dtype=torch.float32, device=grad.device) for _ in range(3))
+    g_one = torch.stack(eig3.eig3_eigvals_backward(a_dev, ones, "general", "fma"), 1)
+    eye9 = torch.tensor([1.0, 0, 0, 0, 1, 0, 0, 0, 1], dtype=torch.float32, device=grad.device)
+    r = (g_one - eye9).abs().max().item()
+    assert r <= 4 * EPS32, r
+    sub = idx[::6]
+    got = grad.index_select(0, torch.from_numpy(sub).to(grad.device)).double().cpu().numpy()
+    ref = np.array([exact.eigvals_vjp(a64[m], g32[m].astype(np.float64)) for m in sub])
+    rel = np.abs(got - ref).max(1) / np.abs(ref).max(1)
+    assert rel.max() <= 4 * EPS32, rel.max()
