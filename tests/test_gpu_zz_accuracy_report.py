@@ -60,10 +60,10 @@ def test_accuracy_report(plain_oracle):
                  **{k: _ratios(gi[:, j], bi[:, j]) for j, k in enumerate(("I1", "J2", "J3", "Delta"))}},
                 {"eigvals": _ratios(lam_errors(t2, o2l)[sel], bl),
                  **{k: _ratios(pi[:, j], bi[:, j]) for j, k in enumerate(("I1", "J2", "J3", "Delta"))}})
-    # the perturbation sweep by bucket: variant x kappa x delta range, 1024
+    # the perturbation sweep by bucket: variant x kappa x delta range, 4096
     # matrices per (variant, kappa), eigenvalues of both modes and of the
     # paper's algorithm against the exact roots (max, p99, p99.99)
-    cb = w.config2(9 * 1024, seed=16)
+    cb = w.config2(9 * 4096, seed=16)
     tb = Truth(cb["a"], cb["kappa"])
     ob = lam_errors(tb, plain_oracle.eigvals(cb["a"])) / tb.bound_lam()
     gb = {acc: lam_errors(tb, download_lam(eig3.eig3_eigvals(upload(cb["a"], "soa"), "general", acc, "soa")))
