@@ -83,7 +83,7 @@ def profile_set():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    c5 = w.config5(N_MAIN)
+    c5 = w.differentiation_batch(N_MAIN)
     a = [torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])).to(dev) for k in range(9)]
     g = [torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])).to(dev) for k in range(3)]
     for acc in ("fma", "compensated"):
@@ -91,7 +91,7 @@ def profile_set():
         eig3.eig3_eigvals_backward(a, g, "general", acc)
     torch.cuda.synchronize()
     del a, g
-    s = w.config3(N_SYM)["s"]
+    s = w.stress_tensors(N_SYM)["s"]
     s64 = [torch.from_numpy(np.ascontiguousarray(s[:, k])).to(dev) for k in range(6)]
     eig3.eig3_eigvals(s64, "symmetric", "fma", "soa")
     s32 = [t.float() for t in s64]
@@ -270,8 +270,8 @@ def main():
 
     # ------------------------------------------------------------ main step
     t0 = time.perf_counter()
-    c5 = w.config5(N_MAIN)
-    log(f"config5 generated n={N_MAIN} in {time.perf_counter() - t0:.1f}s")
+    c5 = w.differentiation_batch(N_MAIN)
+    log(f"differentiation batch generated n={N_MAIN} in {time.perf_counter() - t0:.1f}s")
     a = [torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])).to(dev) for k in range(9)]
     g = [torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])).to(dev) for k in range(3)]
     lam = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(3)]
@@ -323,36 +323,36 @@ def main():
 
     if not args.no_variants:
         for acc_v in ("fma", "compensated"):
-            variant(f"config5 fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
+            variant(f"differentiation batch fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a, "general", acc_v, "soa", out=lam), "f64")
-            variant(f"config5 bwd general f64 {acc_v}", "bwd_general_f64", N_MAIN,
+            variant(f"differentiation batch bwd general f64 {acc_v}", "bwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals_backward(a, g, "general", acc_v, out=grad), "f64")
         # the step with error-free products (within 8x the bounds at every kappa)
-        variant("config5 step f64 (compensated forward + adjoint)", "step_general_f64", N_MAIN,
+        variant("differentiation batch step f64 (compensated forward + adjoint)", "step_general_f64", N_MAIN,
                 lambda: (eig3.eig3_eigvals(a, "general", "compensated", "soa", out=lam),
                          eig3.eig3_eigvals_backward(a, g, "general", "compensated", out=grad)), "f64")
         # eigenprojectors E_1..E_3 (27 outputs per matrix, write-heavy)
         eproj = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(27)]
-        variant("config5 eigenprojectors general f64 fma", "eigenprojectors_general_f64", N_MAIN,
+        variant("differentiation batch eigenprojectors general f64 fma", "eigenprojectors_general_f64", N_MAIN,
                 lambda: eig3.eig3_eigenprojectors(a, "general", "fma", "soa", out=eproj), "f64")
         del eproj
         # a function of each matrix through the eigenprojectors (9 outputs)
         fexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
-        variant("config5 matrix exponential general f64 fma", "matrix_function_general_f64", N_MAIN,
+        variant("differentiation batch matrix exponential general f64 fma", "matrix_function_general_f64", N_MAIN,
                 lambda: eig3.eig3_matrix_function(a, "exp", "general", "fma", out=fexp), "f64")
         gexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
-        variant("config5 matrix exponential adjoint general f64 fma", "matrix_function_backward_general_f64", N_MAIN,
+        variant("differentiation batch matrix exponential adjoint general f64 fma", "matrix_function_backward_general_f64", N_MAIN,
                 lambda: eig3.eig3_matrix_function_backward(a, fexp, "exp", "general", "fma", out=gexp), "f64")
         del fexp, gexp
         # the same batch as one (n, 3, 3) array of structures (LDS-staged loads)
         a_aos = torch.stack(a, dim=1).contiguous()
         lam_aos = torch.empty((N_MAIN, 3), dtype=torch.float64, device=dev)
-        variant("config5 fwd general f64 fma aos", "fwd_general_f64", N_MAIN,
+        variant("differentiation batch fwd general f64 fma aos", "fwd_general_f64", N_MAIN,
                 lambda: eig3.eig3_eigvals(a_aos, "general", "fma", "aos", out=lam_aos), "f64")
         # the adjoint as the autograd Function calls it: g (n, 3), dL/dA (n, 3, 3)
         g_aos = torch.stack(g, dim=1).contiguous()
         grad_aos = torch.empty_like(a_aos)
-        variant("config5 bwd general f64 fma aos", "bwd_general_f64", N_MAIN,
+        variant("differentiation batch bwd general f64 fma aos", "bwd_general_f64", N_MAIN,
                 lambda: eig3.eig3_eigvals_backward(a_aos, g_aos, "general", "fma", out=grad_aos), "f64")
         del a_aos, lam_aos, g_aos, grad_aos
         # the same workload stored in binary32: forward in both evaluations,
@@ -362,44 +362,44 @@ def main():
         lam32 = [torch.empty(N_MAIN, dtype=torch.float32, device=dev) for _ in range(3)]
         grad32 = [torch.empty(N_MAIN, dtype=torch.float32, device=dev) for _ in range(9)]
         for acc_v in ("fma", "compensated"):
-            variant(f"config5 fwd general f32 {acc_v}", "fwd_general_f32", N_MAIN,
+            variant(f"differentiation batch fwd general f32 {acc_v}", "fwd_general_f32", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a32, "general", acc_v, "soa", out=lam32), "f32")
-        variant("config5 bwd general f32", "bwd_general_f32", N_MAIN,
+        variant("differentiation batch bwd general f32", "bwd_general_f32", N_MAIN,
                 lambda: eig3.eig3_eigvals_backward(a32, g32, "general", "fma", out=grad32), "f32")
 
         for acc_v in ("fma", "compensated"):
             def step32(acc_v=acc_v):
                 eig3.eig3_eigvals(a32, "general", acc_v, "soa", out=lam32)
                 eig3.eig3_eigvals_backward(a32, g32, "general", "fma", out=grad32)
-            variant(f"config5 step f32 ({acc_v} forward + adjoint)", "step_general_f32", N_MAIN, step32, "f32")
+            variant(f"differentiation batch step f32 ({acc_v} forward + adjoint)", "step_general_f32", N_MAIN, step32, "f32")
         del a, g, lam, grad, a32, g32, lam32, grad32
         torch.cuda.empty_cache()
-        # perturbation sweep (config 2)
+        # the perturbation sweep
         t0 = time.perf_counter()
-        c2 = w.config2(N_MAIN)
-        log(f"config2 generated in {time.perf_counter() - t0:.1f}s")
+        c2 = w.perturbation_sweep(N_MAIN)
+        log(f"perturbation sweep generated in {time.perf_counter() - t0:.1f}s")
         a2 = [torch.from_numpy(np.ascontiguousarray(c2["a"][:, k])).to(dev) for k in range(9)]
         del c2
         l2 = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(3)]
         for acc_v in ("fma", "compensated"):
-            variant(f"config2 fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
+            variant(f"perturbation sweep fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a2, "general", acc_v, "soa", out=l2), "f64")
         del a2, l2
         torch.cuda.empty_cache()
-        # symmetric stress tensors (configs 3 and 4)
+        # symmetric stress tensors in binary64 and binary32
         t0 = time.perf_counter()
-        c3 = w.config3(N_SYM)
-        log(f"config3 generated in {time.perf_counter() - t0:.1f}s")
+        c3 = w.stress_tensors(N_SYM)
+        log(f"stress tensors generated in {time.perf_counter() - t0:.1f}s")
         s64 = [torch.from_numpy(np.ascontiguousarray(c3["s"][:, k])).to(dev) for k in range(6)]
         l3 = [torch.empty(N_SYM, dtype=torch.float64, device=dev) for _ in range(3)]
         for acc_v in ("fma", "compensated"):
-            variant(f"config3 fwd symmetric f64 {acc_v}", "fwd_symmetric_f64", N_SYM,
+            variant(f"stress tensors fwd symmetric f64 {acc_v}", "fwd_symmetric_f64", N_SYM,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(s64, "symmetric", acc_v, "soa", out=l3), "f64")
         del l3
         # the paper's application: Mohr-Coulomb f and df/dsigma (S_yc = 100, m = 10)
         f_mc = torch.empty(N_SYM, dtype=torch.float64, device=dev)
         g_mc = [torch.empty(N_SYM, dtype=torch.float64, device=dev) for _ in range(6)]
-        variant("config3 mohr-coulomb f + df/dsigma symmetric f64 fma", "mohr_coulomb_symmetric_f64", N_SYM,
+        variant("stress tensors mohr-coulomb f + df/dsigma symmetric f64 fma", "mohr_coulomb_symmetric_f64", N_SYM,
                 lambda: eig3.eig3_mohr_coulomb(s64, 100.0, 10.0, "symmetric", "fma", True, out=(f_mc, g_mc)), "f64")
         del f_mc, g_mc
         s32 = [t.float() for t in s64]
@@ -408,10 +408,10 @@ def main():
         l4 = [torch.empty(N_SYM, dtype=torch.float32, device=dev) for _ in range(3)]
         for acc_v in ("fma", "compensated"):
             try:
-                variant(f"config4 fwd symmetric f32 {acc_v}", "fwd_symmetric_f32", N_SYM,
+                variant(f"binary32 stress tensors fwd symmetric f32 {acc_v}", "fwd_symmetric_f32", N_SYM,
                         lambda acc_v=acc_v: eig3.eig3_eigvals(s32, "symmetric", acc_v, "soa", out=l4), "f32")
             except eig3.Eig3Error as e:
-                log(f"config4 {acc_v}: {e}")
+                log(f"binary32 stress tensors {acc_v}: {e}")
         del s32, l4, c3
         torch.cuda.empty_cache()
 
@@ -420,7 +420,7 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import plain
         sample_n = 1 << 20
-        cs = w.config5(sample_n, seed=w.SEEDS[5] + 1)
+        cs = w.differentiation_batch(sample_n, seed=w.SEEDS["differentiation_batch"] + 1)
         cores = plain.max_threads()
 
         def oracle_rate(threads, seconds, n):
@@ -439,7 +439,7 @@ def main():
         reps1, el1, rate1 = oracle_rate(1, args.cpu_seconds / 4, sample_n >> 4)
         cpu = {"value": rate, "unit": "matrices/s", "cores": cores, "kind": "oracle",
                "sample": f"{reps} passes of forward eigvals + eigenprojector backward over {sample_n} "
-                         f"config-5 matrices (plain binary64 C of the paper's algorithms, OpenMP, "
+                         f"differentiation batch matrices (plain binary64 C of the paper's algorithms, OpenMP, "
                          f"gcc -O2 -ffp-contract=off), {el:.1f} s",
                "single_core": {"value": rate1, "unit": "matrices/s", "cores": 1,
                                "sample": f"{reps1} passes over {sample_n >> 4} matrices, {el1:.1f} s"},

@@ -20,7 +20,7 @@ def eig3():
 
 @pytest.fixture(scope="module")
 def c5():
-    return w.config5(1 << 14, with_basis=True)
+    return w.differentiation_batch(1 << 14, with_basis=True)
 
 
 def _rel(err, ref):
@@ -92,7 +92,7 @@ def test_backward_central_differences(eig3, c5):
 def test_backward_symmetric(eig3, layout):
     """Symmetric storage: gradient with respect to the 6 stored entries equals
     the general gradient with the two off-diagonal positions summed."""
-    s = w.config3(4096, seed=31)["s"]
+    s = w.stress_tensors(4096, seed=31)["s"]
     keep = np.ones(s.shape[0], dtype=bool)
     a = w.symmetric_to_general(s)
     rng = np.random.default_rng(5)

@@ -21,7 +21,7 @@ EXE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_abi", "c_calle
 def test_c_caller_matches_binding_and_oracle(tmp_path, plain_oracle):
     import paper_2511_00292_amd as eig3
     n = 3000  # a ragged tail after 11 full workgroup spans
-    c = w.config5(n, seed=61)
+    c = w.differentiation_batch(n, seed=61)
     f = {k: str(tmp_path / f"{k}.bin") for k in ("a", "g", "lam", "inv", "grad")}
     np.ascontiguousarray(c["a"], dtype=np.float64).tofile(f["a"])
     np.ascontiguousarray(c["g"], dtype=np.float64).tofile(f["g"])

@@ -36,10 +36,10 @@ def eig3():
 def test_bitwise_invariants(eig3, plain_oracle, mode, variant, structure):
     """Plain binary64 in the printed order on both sides: identical bits."""
     if structure == "general":
-        a = np.concatenate([w.config2(3000, seed=61)["a"], w.config1(1000, seed=62)["a"]])
+        a = np.concatenate([w.perturbation_sweep(3000, seed=61)["a"], w.haar_general(1000, seed=62)["a"]])
         dev = upload(a, "aos")
     else:
-        s = w.config3(4000, seed=63)["s"]
+        s = w.stress_tensors(4000, seed=63)["s"]
         a = w.symmetric_to_general(s)
         dev = upload(s, "soa")
     inv = download_inv(eig3.eig3_invariants(dev, structure, mode))
@@ -83,7 +83,7 @@ def test_naive_j3_example(eig3):
 
 def test_comparators_reject_other_calls(eig3):
     import torch
-    a = upload(w.config1(8, seed=1)["a"], "aos")
+    a = upload(w.haar_general(8, seed=1)["a"], "aos")
     g = torch.zeros((8, 3), dtype=torch.float64, device="cuda:0")
     with pytest.raises(eig3.Eig3Error):
         eig3.eig3_eigvals_backward(a, g, "general", "naive")

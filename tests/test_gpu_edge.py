@@ -68,7 +68,7 @@ def test_exact_repeated_roots(eig3, acc):
 
 
 def test_nan_propagates_per_matrix(eig3):
-    c = w.config1(300, seed=5)
+    c = w.haar_general(300, seed=5)
     a = c["a"].copy()
     a[17, 4] = np.nan
     a[200, 2] = np.inf
@@ -95,7 +95,7 @@ def test_complex_spectrum_stays_finite(eig3, acc):
 
 def test_nan_off_diagonal_propagates(eig3):
     """A NaN off-diagonal entry (the trace stays finite) still gives NaN."""
-    c = w.config1(64, seed=5)
+    c = w.haar_general(64, seed=5)
     a = c["a"].copy()
     a[10, 1] = np.nan
     a[20, 7] = np.nan
@@ -119,7 +119,7 @@ def test_zero_matrix_and_empty_batch(eig3):
 @pytest.mark.parametrize("scale", [1e-40, 1e-10, 1e10, 1e40])
 def test_scaling_range(eig3, scale):
     """Delta is a sixth-degree form: entries up to ~1e50 keep it in range."""
-    c = w.config1(500, seed=6)
+    c = w.haar_general(500, seed=6)
     a = c["a"] * scale
     t = Truth(a, c["kappa"])
     lam = download_lam(eig3.eig3_eigvals(upload(a, "aos")))

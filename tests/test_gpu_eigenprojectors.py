@@ -21,7 +21,7 @@ def eig3():
 @pytest.mark.parametrize("out_layout", ["soa", "aos"])
 @pytest.mark.parametrize("acc", ["fma", "compensated"])
 def test_against_exact(eig3, layout, out_layout, acc):
-    c = w.config5(512, seed=81)
+    c = w.differentiation_batch(512, seed=81)
     res = eig3.eig3_eigenprojectors(upload(c["a"], layout), "general", acc, out_layout)
     if out_layout == "aos":
         e = res.cpu().numpy().reshape(-1, 27)
@@ -34,7 +34,7 @@ def test_against_exact(eig3, layout, out_layout, acc):
 
 def test_identities_large_batch(eig3):
     """sum E_k = I and sum lambda_k E_k = A on 2^20 matrices."""
-    c = w.config5(1 << 20, seed=82)
+    c = w.differentiation_batch(1 << 20, seed=82)
     a = upload(c["a"], "aos")
     e = eig3.eig3_eigenprojectors(a).cpu().numpy().reshape(-1, 3, 3, 3)
     lam = eig3.eig3_eigvals(a).cpu().numpy()
@@ -46,7 +46,7 @@ def test_identities_large_batch(eig3):
 
 
 def test_symmetric_components(eig3):
-    s = w.config3(2048, seed=83)["s"]
+    s = w.stress_tensors(2048, seed=83)["s"]
     s = s[np.abs(s[:, 3:]).max(1) > 1.0]  # the generic half: well-separated spectra
     eg = eig3.eig3_eigenprojectors(upload(w.symmetric_to_general(s), "aos")).cpu().numpy()
     es = eig3.eig3_eigenprojectors(upload(s, "aos"), "symmetric").cpu().numpy()
@@ -57,7 +57,7 @@ def test_symmetric_components(eig3):
 def test_matrix_exponential(eig3):
     """exp(A) = sum_k exp(lambda_k) E_k against scipy.linalg.expm."""
     import scipy.linalg
-    c = w.config5(256, seed=84)
+    c = w.differentiation_batch(256, seed=84)
     a = upload(c["a"], "aos")
     e = eig3.eig3_eigenprojectors(a).cpu().numpy().reshape(-1, 3, 3, 3)
     lam = eig3.eig3_eigvals(a).cpu().numpy()

@@ -25,7 +25,7 @@ def eig3():
 
 @pytest.fixture(scope="module")
 def c4():
-    c = w.config4(1500)
+    c = w.stress_tensors_f32(1500)
     s = c["s"]  # float32
     a = w.symmetric_to_general(s.astype(np.float64))
     return s, Truth(a, np.ones(a.shape[0]))
@@ -33,22 +33,22 @@ def c4():
 
 @pytest.fixture(scope="module")
 def c1f():
-    c = w.config1(1500)
+    c = w.haar_general(1500)
     a32 = c["a"].astype(np.float32)
     return a32, Truth(a32.astype(np.float64), c["kappa"])
 
 
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-def test_config4_symmetric_f32(eig3, c4, acc, layout):
+def test_stress_tensors_f32_symmetric_f32(eig3, c4, acc, layout):
     s, t = c4
     lam = download_lam(eig3.eig3_eigvals(upload(s, layout), "symmetric", acc, "soa"))
-    check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"config4 f32 eigvals {acc} {layout}")
+    check(lam_errors(t, lam), t.bound_lam(EPS32), what=f"binary32 stress tensors f32 eigvals {acc} {layout}")
     assert np.all(np.diff(lam, axis=1) >= 0)
 
 
 @pytest.mark.parametrize("acc", ACCS)
-def test_config4_invariants_f32(eig3, c4, acc):
+def test_stress_tensors_f32_invariants_f32(eig3, c4, acc):
     """I1 and J2 everywhere; J3 and Delta where the result is a binary32
     normal number (below, the subnormal spacing exceeds the bound)."""
     s, t = c4
@@ -57,7 +57,7 @@ def test_config4_invariants_f32(eig3, c4, acc):
     b = t.bound_inv(EPS32)
     normal = np.abs(t.inv) >= F32_TINY
     normal[:, :2] = True
-    check(np.where(normal, err, 0.0), b, what=f"config4 f32 invariants {acc}")
+    check(np.where(normal, err, 0.0), b, what=f"binary32 stress tensors f32 invariants {acc}")
 
 
 @pytest.mark.parametrize("acc", ACCS)
@@ -70,7 +70,7 @@ def test_general_f32(eig3, c1f, acc, layout):
 
 @pytest.mark.parametrize("n", [1, 63, 257, 1000])
 def test_f32_ragged(eig3, n):
-    c = w.config4(n, seed=91)
+    c = w.stress_tensors_f32(n, seed=91)
     s = c["s"]
     t = Truth(w.symmetric_to_general(s.astype(np.float64)), np.ones(n))
     for acc in ACCS:
@@ -90,10 +90,10 @@ def test_f32_two_per_lane(eig3, structure, acc):
     import torch
     for n in (1, 2, 511, 512, 513, 1024 + 37, 5 * 512):
         if structure == "symmetric":
-            a32 = w.config4(n, seed=95)["s"]
+            a32 = w.stress_tensors_f32(n, seed=95)["s"]
             t = Truth(w.symmetric_to_general(a32.astype(np.float64)), np.ones(n))
         else:
-            c = w.config1(n, seed=95)
+            c = w.haar_general(n, seed=95)
             a32 = c["a"].astype(np.float32)
             t = Truth(a32.astype(np.float64), c["kappa"])
         aligned = [x.clone() for x in upload(a32, "soa")]  # own allocations
@@ -113,7 +113,7 @@ def test_f32_two_per_lane(eig3, structure, acc):
 def test_f32_backward(eig3, layout):
     """binary32 adjoint: binary64 arithmetic on the widened entries, rounded
     once; against the exact gradient at the binary32 input."""
-    c = w.config5(2048, seed=33)
+    c = w.differentiation_batch(2048, seed=33)
     a32 = c["a"].astype(np.float32)
     g32 = c["g"].astype(np.float32)
     from gpu_util import download_matrix
@@ -122,7 +122,7 @@ def test_f32_backward(eig3, layout):
     ref = np.array([exact.eigvals_vjp(a32[m].astype(np.float64), g32[m].astype(np.float64)) for m in idx])
     rel = np.abs(grad[idx] - ref).max(1) / np.abs(ref).max(1)
     assert rel.max() <= 4 * EPS32, rel.max()
-    s = w.config3(1024, seed=34)["s"].astype(np.float32)
+    s = w.stress_tensors(1024, seed=34)["s"].astype(np.float32)
     gs = np.random.default_rng(3).standard_normal((1024, 3)).astype(np.float32)
     gsym = download_matrix(eig3.eig3_eigvals_backward(upload(s, layout), upload(gs, "soa"), "symmetric"), 6)
     assert np.isfinite(gsym[np.abs(gsym).max(1) < 1e30]).all()
@@ -203,7 +203,7 @@ def test_eigenprojectors_f32(eig3, layout):
     """binary32 eigenprojectors: binary64 arithmetic on the widened entries,
     rounded once; against the exact Frobenius covariants of the binary32
     input (well-separated spectra, kappa <= 100)."""
-    c = w.config5(256, seed=85)
+    c = w.differentiation_batch(256, seed=85)
     a32 = c["a"].astype(np.float32)
     e = eig3.eig3_eigenprojectors(upload(a32, layout), "general", "fma", "aos").double().cpu().numpy()
     e = e.reshape(-1, 27)

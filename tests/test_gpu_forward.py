@@ -20,26 +20,26 @@ def eig3():
 
 @pytest.fixture(scope="module")
 def c1():
-    c = w.config1(1200)
+    c = w.haar_general(1200)
     return c, Truth(c["a"], c["kappa"])
 
 
 @pytest.fixture(scope="module")
 def c2():
-    c = w.config2(9 * 200)
+    c = w.perturbation_sweep(9 * 200)
     return c, Truth(c["a"], c["kappa"])
 
 
 @pytest.fixture(scope="module")
 def c3():
-    c = w.config3(1200)
+    c = w.stress_tensors(1200)
     a = w.symmetric_to_general(c["s"])
     return c, Truth(a, np.ones(a.shape[0]))
 
 
 @pytest.fixture(scope="module")
 def c5():
-    c = w.config5(1200)
+    c = w.differentiation_batch(1200)
     return c, Truth(c["a"], c["kappa"])
 
 
@@ -51,24 +51,24 @@ def plain(plain_oracle):
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("layout", ["soa", "aos"])
 @pytest.mark.parametrize("out_layout", ["soa", "aos"])
-def test_config1_eigvals(eig3, c1, acc, layout, out_layout):
+def test_haar_general_eigvals(eig3, c1, acc, layout, out_layout):
     c, t = c1
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], layout), "general", acc, out_layout))
-    check(lam_errors(t, lam), t.bound_lam(), what=f"config1 eigvals {acc} {layout}->{out_layout}")
+    check(lam_errors(t, lam), t.bound_lam(), what=f"Haar-similar batch eigvals {acc} {layout}->{out_layout}")
     assert np.all(np.diff(lam, axis=1) >= 0)
 
 
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-def test_config1_invariants(eig3, c1, acc, layout):
+def test_haar_general_invariants(eig3, c1, acc, layout):
     c, t = c1
     inv = download_inv(eig3.eig3_invariants(upload(c["a"], layout), "general", acc))
-    check(inv_errors(t, inv), t.bound_inv(), what=f"config1 invariants {acc} {layout}")
+    check(inv_errors(t, inv), t.bound_inv(), what=f"Haar-similar batch invariants {acc} {layout}")
 
 
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("kappa", [1.0, 10.0, 100.0])
-def test_config2_buckets(eig3, plain, c2, acc, kappa):
+def test_perturbation_sweep_buckets(eig3, plain, c2, acc, kappa):
     """Perturbation sweep: all three spectra, delta in [1e-16, 1e-1]."""
     c, t = c2
     sel = c["kappa"] == kappa
@@ -85,39 +85,39 @@ def test_config2_buckets(eig3, plain, c2, acc, kappa):
     # differences and error-free products); fma: the paper's class, G2 where
     # the paper's own algorithm exceeds the bounds
     if kappa <= 10.0 or acc == "compensated":
-        check(el, np.broadcast_to(bl, el.shape), what=f"config2 eigvals kappa={kappa} {acc} (G1)")
+        check(el, np.broadcast_to(bl, el.shape), what=f"perturbation sweep eigvals kappa={kappa} {acc} (G1)")
     else:
-        check_g2(el, bl, al, what=f"config2 eigvals kappa={kappa} {acc} (G2)", pool=True)
+        check_g2(el, bl, al, what=f"perturbation sweep eigvals kappa={kappa} {acc} (G2)", pool=True)
     if kappa == 1.0 or acc == "compensated":
-        check(ei, bi, what=f"config2 invariants kappa={kappa} {acc} (G1)")
+        check(ei, bi, what=f"perturbation sweep invariants kappa={kappa} {acc} (G1)")
     else:
-        check_g2(ei, bi, ai, what=f"config2 invariants kappa={kappa} {acc} (G2)")
+        check_g2(ei, bi, ai, what=f"perturbation sweep invariants kappa={kappa} {acc} (G2)")
 
 
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-def test_config3_symmetric(eig3, c3, acc, layout):
+def test_stress_tensors_symmetric(eig3, c3, acc, layout):
     c, t = c3
     s = upload(c["s"], layout)
     lam = download_lam(eig3.eig3_eigvals(s, "symmetric", acc, "soa"))
-    check(lam_errors(t, lam), t.bound_lam(), what=f"config3 eigvals {acc} {layout}")
+    check(lam_errors(t, lam), t.bound_lam(), what=f"stress tensors eigvals {acc} {layout}")
     inv = download_inv(eig3.eig3_invariants(s, "symmetric", acc))
-    check(inv_errors(t, inv), t.bound_inv(), what=f"config3 invariants {acc} {layout}")
+    check(inv_errors(t, inv), t.bound_inv(), what=f"stress tensors invariants {acc} {layout}")
     assert np.all(inv[:, 3] >= 0)
 
 
 @pytest.mark.parametrize("acc", ACCS)
-def test_config5_forward(eig3, plain, c5, acc):
+def test_differentiation_batch_forward(eig3, plain, c5, acc):
     c, t = c5
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], "aos"), "general", acc, "aos"))
     el = lam_errors(t, lam)
     bl = np.broadcast_to(t.bound_lam(), el.shape)
     well = (c["kappa"] <= 10) | (acc == "compensated")
-    check(el[well], bl[well], what=f"config5 eigvals kappa<=10 or compensated {acc} (G1)")
+    check(el[well], bl[well], what=f"differentiation batch eigvals kappa<=10 or compensated {acc} (G1)")
     if well.all():
         return
     al = lam_errors(t, plain.eigvals(c["a"]))
-    check_g2(el[~well], bl[~well], al[~well], what=f"config5 eigvals kappa>10 {acc} (G2)", pool=True)
+    check_g2(el[~well], bl[~well], al[~well], what=f"differentiation batch eigvals kappa>10 {acc} (G2)", pool=True)
 
 
 @pytest.mark.parametrize("acc", ACCS)
@@ -139,11 +139,11 @@ def test_paper_paths(eig3, acc):
 @pytest.mark.parametrize("layout", ["soa", "aos"])
 def test_ragged_sizes(eig3, n, layout):
     """Sizes around the 64-lane wave and the 256-lane workgroup (LDS tile)."""
-    c = w.config1(n, seed=99)
+    c = w.haar_general(n, seed=99)
     t = Truth(c["a"], c["kappa"])
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], layout), "general", "fma", "aos"))
     check(lam_errors(t, lam), t.bound_lam(), what=f"ragged n={n} {layout}")
-    s = w.config3(n, seed=98)
+    s = w.stress_tensors(n, seed=98)
     ts = Truth(w.symmetric_to_general(s["s"]), np.ones(n))
     lam = download_lam(eig3.eig3_eigvals(upload(s["s"], layout), "symmetric", "fma", "soa"))
     check(lam_errors(ts, lam), ts.bound_lam(), what=f"ragged symmetric n={n} {layout}")
@@ -152,7 +152,7 @@ def test_ragged_sizes(eig3, n, layout):
 def test_aos_unaligned_offset(eig3):
     """AoS input starting at an odd element offset of a larger buffer."""
     import torch
-    c = w.config1(700, seed=97)
+    c = w.haar_general(700, seed=97)
     t = Truth(c["a"], c["kappa"])
     big = torch.zeros(700 * 9 + 5, dtype=torch.float64, device="cuda:0")
     big[3:3 + 700 * 9] = torch.from_numpy(c["a"].ravel()).to("cuda:0")

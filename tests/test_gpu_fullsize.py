@@ -27,9 +27,9 @@ def _properties(a_gen, lam, kappa):
 
 
 @pytest.mark.parametrize("acc", ["fma", "compensated"])
-def test_config2_full_2p24_sampled(eig3, plain_oracle, acc):
+def test_perturbation_sweep_full_2p24_sampled(eig3, plain_oracle, acc):
     n = 1 << 24
-    c = w.config2(n)
+    c = w.perturbation_sweep(n)
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], "soa"), "general", acc, "soa"))
     _properties(c["a"], lam, c["kappa"][:, None][:, 0])
     rng = np.random.default_rng(7)
@@ -38,23 +38,23 @@ def test_config2_full_2p24_sampled(eig3, plain_oracle, acc):
     el = lam_errors(t, lam[idx])
     bl = np.broadcast_to(t.bound_lam(), el.shape)
     good = (c["kappa"][idx] <= 10) | (acc == "compensated")
-    check(el[good], bl[good], what=f"config2 2^24 kappa<=10 or compensated {acc}")
+    check(el[good], bl[good], what=f"perturbation sweep 2^24 kappa<=10 or compensated {acc}")
     if good.all():
         return
     al = lam_errors(t, plain_oracle.eigvals(c["a"][idx]))
-    check_g2(el[~good], bl[~good], al[~good], what=f"config2 2^24 kappa=100 {acc} (G2)", pool=True)
+    check_g2(el[~good], bl[~good], al[~good], what=f"perturbation sweep 2^24 kappa=100 {acc} (G2)", pool=True)
 
 
-def test_config3_full_2p27_sampled(eig3):
+def test_stress_tensors_full_2p27_sampled(eig3):
     n = 1 << 27
-    c = w.config3(n)
+    c = w.stress_tensors(n)
     s = c["s"]
     lam = download_lam(eig3.eig3_eigvals(upload(s, "soa"), "symmetric", "fma", "soa"))
     rng = np.random.default_rng(8)
     idx = np.sort(rng.choice(n, 1500, replace=False))
     a = w.symmetric_to_general(s[idx])
     t = Truth(a, np.ones(idx.size))
-    check(lam_errors(t, lam[idx]), t.bound_lam(), what="config3 2^27 sampled")
+    check(lam_errors(t, lam[idx]), t.bound_lam(), what="stress tensors 2^27 sampled")
     assert np.isfinite(lam).all()
     assert np.all(np.diff(lam, axis=1) >= 0)
     tr = s[:, 0] + s[:, 1] + s[:, 2]
@@ -63,10 +63,10 @@ def test_config3_full_2p27_sampled(eig3):
 
 
 @pytest.mark.parametrize("acc", ["fma", "compensated"])
-def test_config4_full_2p27_f32_sampled(eig3, acc):
+def test_stress_tensors_f32_full_2p27_f32_sampled(eig3, acc):
     from accuracy import EPS32
     n = 1 << 27
-    s = w.config4(n)["s"]
+    s = w.stress_tensors_f32(n)["s"]
     lam = download_lam(eig3.eig3_eigvals(upload(s, "soa"), "symmetric", acc, "soa"))
     assert np.isfinite(lam).all()
     assert np.all(np.diff(lam, axis=1) >= 0)
@@ -74,10 +74,10 @@ def test_config4_full_2p27_f32_sampled(eig3, acc):
     idx = np.sort(rng.choice(n, 1500, replace=False))
     a = w.symmetric_to_general(s[idx].astype(np.float64))
     t = Truth(a, np.ones(idx.size))
-    check(lam_errors(t, lam[idx]), t.bound_lam(EPS32), what=f"config4 2^27 f32 sampled {acc}")
+    check(lam_errors(t, lam[idx]), t.bound_lam(EPS32), what=f"binary32 stress tensors 2^27 f32 sampled {acc}")
 
 
-def test_config5_full_2p24_step(eig3, plain_oracle):
+def test_differentiation_batch_full_2p24_step(eig3, plain_oracle):
     """The benchmark's step at its size and launch shape: eig3_eigvals and
     eig3_eigvals_backward on 2^24 general binary64 matrices, structure of
     arrays.  Forward: sampled outputs against the exact oracle (G1 for
@@ -94,7 +94,7 @@ def test_config5_full_2p24_step(eig3, plain_oracle):
     from gpu_util import download_matrix
     from oracle import exact
     n = 1 << 24
-    c = w.config5(n, with_basis=True)
+    c = w.differentiation_batch(n, with_basis=True)
     a_dev = upload(c["a"], "soa")
     g_dev = upload(c["g"], "soa")
     lam = download_lam(eig3.eig3_eigvals(a_dev, "general", "fma", "soa"))
@@ -109,10 +109,10 @@ def test_config5_full_2p24_step(eig3, plain_oracle):
     el = lam_errors(t, lam[idx])
     bl = np.broadcast_to(t.bound_lam(), el.shape)
     well = c["kappa"][idx] <= 10
-    check(el[well], bl[well], what="config5 2^24 kappa<=10 (G1)")
+    check(el[well], bl[well], what="differentiation batch 2^24 kappa<=10 (G1)")
     al = lam_errors(t, plain_oracle.eigvals(c["a"][idx]))
-    check_g2(el[~well], bl[~well], al[~well], what="config5 2^24 kappa>10 (G2)", pool=True)
-    check(lam_errors(t, lam_c[idx]), bl, what="config5 2^24 compensated, every kappa (G1)")
+    check_g2(el[~well], bl[~well], al[~well], what="differentiation batch 2^24 kappa>10 (G2)", pool=True)
+    check(lam_errors(t, lam_c[idx]), bl, what="differentiation batch 2^24 compensated, every kappa (G1)")
 
     grad_p = plain_oracle.eigvals_backward(c["a"], c["g"])
     v = c["v"].reshape(-1, 3, 3)
@@ -134,7 +134,7 @@ def test_config5_full_2p24_step(eig3, plain_oracle):
     assert rc.max() <= min(r.max(), 2.0 * rp.max() + 1e-8), (rc.max(), r.max(), rp.max())
 
 
-def test_config5_full_2p24_matrix_exp_and_projectors(eig3):
+def test_differentiation_batch_full_2p24_matrix_exp_and_projectors(eig3):
     """The matrix exponential, its adjoint and the eigenprojectors at the
     benchmark's size and launch shape (2^24 general binary64 matrices,
     structure of arrays).  Sampled outputs against the exact oracle
@@ -143,7 +143,7 @@ def test_config5_full_2p24_matrix_exp_and_projectors(eig3):
     import torch
     from oracle import exact
     n = 1 << 24
-    c = w.config5(n, seed=5)
+    c = w.differentiation_batch(n, seed=5)
     a_dev = upload(c["a"], "soa")
     f = torch.stack(eig3.eig3_matrix_function(a_dev, "exp", "general", "fma"), 1)
     eye = [torch.full((n,), float(k in (0, 4, 8)), dtype=torch.float64, device=f.device) for k in range(9)]
@@ -179,7 +179,7 @@ def test_config5_full_2p24_matrix_exp_and_projectors(eig3):
         assert np.abs(e_s[j] - ref).max() <= 1e-8 * np.abs(ref).max(), int(m)
 
 
-def test_config3_full_2p27_mohr_coulomb(eig3):
+def test_stress_tensors_full_2p27_mohr_coulomb(eig3):
     """Mohr-Coulomb f and df/dsigma at the benchmark's size and launch shape
     (2^27 symmetric binary64 stress tensors, S_yc = 100, m = 10).  Sampled
     outputs against the exact oracle; on every output two identities of the
@@ -196,7 +196,7 @@ def test_config3_full_2p27_mohr_coulomb(eig3):
     from oracle import exact
     n = 1 << 27
     syc, mm = 100.0, 10.0
-    s = w.config3(n)["s"]
+    s = w.stress_tensors(n)["s"]
     s_dev = upload(s, "soa")
     f, dfds = eig3.eig3_mohr_coulomb(s_dev, syc, mm, "symmetric", "fma")
     g = torch.stack(dfds, 1)
@@ -240,7 +240,7 @@ def test_config3_full_2p27_mohr_coulomb(eig3):
 
 
 @pytest.mark.parametrize("acc", ["fma", "compensated"])
-def test_config5_full_2p24_f32(eig3, acc):
+def test_differentiation_batch_full_2p24_f32(eig3, acc):
     """The benchmark's binary32 step at its size and launch shape: 2^24
     general matrices of the differentiation batch stored in binary32,
     structure of arrays (two matrices per lane in the forward).  Forward:
@@ -253,7 +253,7 @@ def test_config5_full_2p24_f32(eig3, acc):
     from oracle import exact
     from accuracy import EPS32
     n = 1 << 24
-    c = w.config5(n, seed=6)
+    c = w.differentiation_batch(n, seed=6)
     a32 = c["a"].astype(np.float32)
     g32 = c["g"].astype(np.float32)
     a_dev = upload(a32, "soa")
@@ -266,7 +266,7 @@ def test_config5_full_2p24_f32(eig3, acc):
     rng = np.random.default_rng(12)
     idx = np.sort(rng.choice(n, 1200, replace=False))
     t = Truth(a64[idx], c["kappa"][idx])
-    check(lam_errors(t, lam[idx].astype(np.float64)), t.bound_lam(EPS32), what=f"config5 2^24 f32 {acc} (G1)")
+    check(lam_errors(t, lam[idx].astype(np.float64)), t.bound_lam(EPS32), what=f"differentiation batch 2^24 f32 {acc} (G1)")
     if acc != "fma":
         return
     g_dev = upload(g32, "soa")

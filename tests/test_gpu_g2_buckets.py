@@ -1,5 +1,5 @@
 """Truth subsets of 4096 matrices for every (spectrum, kappa) bucket of the
-perturbation sweep: the config-2 generator's three spectra (1, 1+d, 1+2d;
+perturbation sweep: its three spectra (1, 1+d, 1+2d;
 1, 1, 1+d; I + d S) times kappa(V) in {1, 10, 100}, d = 10^U(-16, -1),
 9 x 4096 = 36 864 matrices against the exact invariants and 80-digit
 eigenvalues of the stored matrices.  Gates per bucket: `compensated`
@@ -22,7 +22,7 @@ SPECTRA = ("diag(1, 1+d, 1+2d)", "diag(1, 1, 1+d)", "I + d S")
 
 @pytest.fixture(scope="module")
 def sweep(plain_oracle):
-    c = w.config2(9 * PER_BUCKET)
+    c = w.perturbation_sweep(9 * PER_BUCKET)
     t = Truth(c["a"], c["kappa"])
     o1_lam = plain_oracle.eigvals(c["a"])
     o1_inv = np.stack(plain_oracle.invariants(c["a"]), axis=1)

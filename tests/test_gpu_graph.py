@@ -24,9 +24,9 @@ def test_step_graph_replay():
     import paper_2511_00292_amd as eig3
     dev = torch.device("cuda:0")
     n, ns = 4096 + 77, 2048 + 5
-    c = w.config5(n, seed=61)
+    c = w.differentiation_batch(n, seed=61)
     a, g = _cols(c["a"], dev), _cols(c["g"], dev)
-    s32 = _cols(w.config4(ns, seed=62)["s"], dev)
+    s32 = _cols(w.stress_tensors_f32(ns, seed=62)["s"], dev)
     lam = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
     grad = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(9)]
     l32 = [torch.empty(ns, dtype=torch.float32, device=dev) for _ in range(3)]
@@ -60,7 +60,7 @@ def test_step_graph_replay():
         for k, (x, r) in enumerate(zip(outs, ref)):
             assert torch.equal(x, r), (rep, k)
     # new inputs in the captured buffers: a replay computes on them
-    c2 = w.config5(n, seed=63)
+    c2 = w.differentiation_batch(n, seed=63)
     for dst, src in zip(a, _cols(c2["a"], dev)):
         dst.copy_(src)
     for dst, src in zip(g, _cols(c2["g"], dev)):

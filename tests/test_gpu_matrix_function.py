@@ -43,7 +43,7 @@ def _rel(got, ref):
 @pytest.mark.parametrize("acc", ["fma", "compensated"])
 def test_exp_general(eig3, layout, acc):
     """exp on the differentiation batch (kappa <= 100, gaps >= 1e-3)."""
-    c = w.config5(1000, seed=91)
+    c = w.differentiation_batch(1000, seed=91)
     res = download_matrix(eig3.eig3_matrix_function(upload(c["a"], layout), "exp", "general", acc), 9)
     for m in range(0, 1000, 8):
         assert _rel(res[m], np.array(exact.matrix_function(c["a"][m], "exp"))) <= 1e-12, m
@@ -140,7 +140,7 @@ def test_defective_jordan_blocks(eig3, fn):
 def test_binary32_storage(eig3):
     """binary32 storage: binary64 arithmetic on the widened entries, rounded
     once; against the exact f of the binary32 input."""
-    c = w.config5(512, seed=94)
+    c = w.differentiation_batch(512, seed=94)
     a32 = c["a"].astype(np.float32)
     res = download_matrix(eig3.eig3_matrix_function(upload(a32, "aos"), "exp"), 9)
     for m in range(0, 512, 8):
@@ -149,7 +149,7 @@ def test_binary32_storage(eig3):
 
 
 def test_rejects(eig3):
-    c = w.config1(16, seed=95)
+    c = w.haar_general(16, seed=95)
     with pytest.raises(ValueError):
         eig3.eig3_matrix_function(upload(c["a"], "aos"), "sin")
     with pytest.raises(eig3.Eig3Error):
@@ -161,7 +161,7 @@ def test_rejects(eig3):
 def test_backward_exp_general(eig3, layout, acc):
     """d<G, exp(A)>/dA against the exact Daleckii-Krein product (kappa <= 100,
     gaps >= 1e-3)."""
-    c = w.config5(600, seed=96)
+    c = w.differentiation_batch(600, seed=96)
     g = np.random.default_rng(97).standard_normal((600, 9))
     res = download_matrix(eig3.eig3_matrix_function_backward(upload(c["a"], layout), upload(g, layout), "exp",
                                                              "general", acc), 9)
@@ -194,7 +194,7 @@ def test_autograd_against_torch_matrix_exp(eig3):
     torch.linalg.matrix_exp and torch's autograd of it (an independent
     algorithm) on 4096 matrices of the differentiation batch."""
     import torch
-    c = w.config5(4096, seed=100)
+    c = w.differentiation_batch(4096, seed=100)
     a0 = torch.tensor(c["a"].reshape(-1, 3, 3), dtype=torch.float64, device="cuda:0")
     wgt = torch.tensor(np.random.default_rng(101).standard_normal((4096, 3, 3)), dtype=torch.float64,
                        device="cuda:0")

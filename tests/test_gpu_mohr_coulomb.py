@@ -49,7 +49,7 @@ def _pi_plane(n, j2):
 def test_random_stress_states(eig3, layout, dtype):
     g = _golden()
     syc, m = g["S_yc"], g["S_yc"] / g["S_yt"]
-    s = w.config3(600, seed=71)["s"]
+    s = w.stress_tensors(600, seed=71)["s"]
     s = s[np.abs(s).max(1) < 1e3]  # the generic half and the near-isotropic half
     eps = EPS64
     if dtype == "f32":
@@ -76,7 +76,7 @@ def test_random_stress_states(eig3, layout, dtype):
 def test_general_structure_and_no_gradient(eig3):
     g = _golden()
     syc, m = g["S_yc"], g["S_yc"] / g["S_yt"]
-    c = w.config1(300, seed=72)
+    c = w.haar_general(300, seed=72)
     f_only, none = eig3.eig3_mohr_coulomb(upload(c["a"], "aos"), syc, m, "general", grad=False)
     assert none is None
     f, grad = eig3.eig3_mohr_coulomb(upload(c["a"], "aos"), syc, m, "general")
@@ -107,7 +107,7 @@ def test_pi_plane_naive_vs_stable(eig3):
 
 
 def test_invalid_parameters(eig3):
-    s = upload(w.config3(8, seed=1)["s"], "aos")
+    s = upload(w.stress_tensors(8, seed=1)["s"], "aos")
     for syc, m in ((0.0, 10.0), (100.0, -1.0), (float("nan"), 2.0)):
         with pytest.raises(eig3.Eig3Error):
             eig3.eig3_mohr_coulomb(s, syc, m, "symmetric")

@@ -35,15 +35,15 @@ def test_accuracy_report(plain_oracle):
         d.update(extra or {})
         rep["rows"].append(d)
 
-    # config 1 and the perturbation sweep buckets (general binary64)
-    c1 = w.config1(1500, seed=12)
+    # Haar-similar batch and the perturbation sweep buckets (general binary64)
+    c1 = w.haar_general(1500, seed=12)
     t1 = Truth(c1["a"], c1["kappa"])
     o1 = plain_oracle.eigvals(c1["a"])
     for acc in ("fma", "compensated"):
         lam = download_lam(eig3.eig3_eigvals(upload(c1["a"], "soa"), "general", acc, "soa"))
-        row(f"config1 general f64 eigvals ({acc})", 1500, _ratios(lam_errors(t1, lam), t1.bound_lam()),
+        row(f"Haar-similar batch general f64 eigvals ({acc})", 1500, _ratios(lam_errors(t1, lam), t1.bound_lam()),
             _ratios(lam_errors(t1, o1), t1.bound_lam()))
-    c2 = w.config2(9 * 300, seed=13)
+    c2 = w.perturbation_sweep(9 * 300, seed=13)
     t2 = Truth(c2["a"], c2["kappa"])
     o2l = plain_oracle.eigvals(c2["a"])
     o2i = np.stack(plain_oracle.invariants(c2["a"]), axis=1)
@@ -55,7 +55,7 @@ def test_accuracy_report(plain_oracle):
             bl, bi = t2.bound_lam()[sel], t2.bound_inv()[sel]
             gi = inv_errors(t2, inv)[sel]
             pi = inv_errors(t2, o2i)[sel]
-            row(f"config2 kappa={kappa:g} general f64 ({acc})", int(sel.sum()),
+            row(f"perturbation sweep kappa={kappa:g} general f64 ({acc})", int(sel.sum()),
                 {"eigvals": _ratios(lam_errors(t2, lam)[sel], bl),
                  **{k: _ratios(gi[:, j], bi[:, j]) for j, k in enumerate(("I1", "J2", "J3", "Delta"))}},
                 {"eigvals": _ratios(lam_errors(t2, o2l)[sel], bl),
@@ -63,7 +63,7 @@ def test_accuracy_report(plain_oracle):
     # the perturbation sweep by bucket: variant x kappa x delta range, 4096
     # matrices per (variant, kappa), eigenvalues of both modes and of the
     # paper's algorithm against the exact roots (max, p99, p99.99)
-    cb = w.config2(9 * 4096, seed=16)
+    cb = w.perturbation_sweep(9 * 4096, seed=16)
     tb = Truth(cb["a"], cb["kappa"])
     ob = lam_errors(tb, plain_oracle.eigvals(cb["a"])) / tb.bound_lam()
     gb = {acc: lam_errors(tb, download_lam(eig3.eig3_eigvals(upload(cb["a"], "soa"), "general", acc, "soa")))
@@ -85,24 +85,24 @@ def test_accuracy_report(plain_oracle):
                                "p9999": float(np.percentile(x, 99.99))}
                 rep["buckets"].append({"variant": names[v], "kappa": kappa, "delta": [lo, hi],
                                        "n": int(sel.sum()), **st})
-    # config 3 (symmetric binary64) and config 4 (binary32)
-    c3 = w.config3(1500, seed=14)
+    # stress tensors (symmetric binary64) and binary32 stress tensors (binary32)
+    c3 = w.stress_tensors(1500, seed=14)
     a3 = w.symmetric_to_general(c3["s"])
     t3 = Truth(a3, np.ones(1500))
     o3 = plain_oracle.eigvals(a3)
     for acc in ("fma", "compensated"):
         lam = download_lam(eig3.eig3_eigvals(upload(c3["s"], "soa"), "symmetric", acc, "soa"))
-        row(f"config3 symmetric f64 eigvals ({acc})", 1500, _ratios(lam_errors(t3, lam), t3.bound_lam()),
+        row(f"stress tensors symmetric f64 eigvals ({acc})", 1500, _ratios(lam_errors(t3, lam), t3.bound_lam()),
             _ratios(lam_errors(t3, o3), t3.bound_lam()))
     s4 = c3["s"].astype(np.float32)
     a4 = w.symmetric_to_general(s4.astype(np.float64))
     t4 = Truth(a4, np.ones(1500))
     for acc in ("fma", "compensated"):
         lam = download_lam(eig3.eig3_eigvals(upload(s4, "soa"), "symmetric", acc, "soa"))
-        row(f"config4 symmetric f32 eigvals ({acc})", 1500, _ratios(lam_errors(t4, lam), t4.bound_lam(EPS32)),
+        row(f"binary32 stress tensors symmetric f32 eigvals ({acc})", 1500, _ratios(lam_errors(t4, lam), t4.bound_lam(EPS32)),
             extra={"bound_eps": "2^-24"})
-    # config 5 forward and backward
-    c5 = w.config5(1500, seed=15, with_basis=True)
+    # differentiation batch forward and backward
+    c5 = w.differentiation_batch(1500, seed=15, with_basis=True)
     t5 = Truth(c5["a"], c5["kappa"])
     o5 = plain_oracle.eigvals(c5["a"])
     idx = np.arange(0, 1500, 10)
@@ -114,7 +114,7 @@ def test_accuracy_report(plain_oracle):
                                                           "general", acc), 9)
         rel = np.abs(grad - gref).max(1) / np.abs(gref).max(1)
         relp = np.abs(ob - gref).max(1) / np.abs(gref).max(1)
-        row(f"config5 general f64 ({acc})", 1500, {"eigvals": _ratios(lam_errors(t5, lam), t5.bound_lam()),
+        row(f"differentiation batch general f64 ({acc})", 1500, {"eigvals": _ratios(lam_errors(t5, lam), t5.bound_lam()),
                                                     "grad_rel_err_max": float(rel.max())},
             {"eigvals": _ratios(lam_errors(t5, o5), t5.bound_lam()), "grad_rel_err_max": float(relp.max())})
     path = os.environ.get("EIG3_ACCURACY_REPORT")

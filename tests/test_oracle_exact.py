@@ -157,7 +157,7 @@ def test_gradient_identities():
     eigenprojectors against powers of the eigenvalues)."""
     rng = np.random.default_rng(15)
     import workloads as w
-    c = w.config5(6, seed=77)
+    c = w.differentiation_batch(6, seed=77)
     for a in c["a"]:
         lam = [float(x) for x in exact.eigvals(a)]
         am = np.array(a).reshape(3, 3)
@@ -171,7 +171,7 @@ def test_gradient_eigenvector_formula_and_fd():
     """d(lambda_i) = y_i^T dA x_i / (y_i^T x_i) with x_i = V[:, i], y_i^T = V^-1[i, :]
     from the generator; and central differences of the exact eigenvalues."""
     import workloads as w
-    c = w.config5(5, seed=78, with_basis=True)
+    c = w.differentiation_batch(5, seed=78, with_basis=True)
     rng = np.random.default_rng(16)
     for m in range(5):
         a = c["a"][m]
@@ -270,7 +270,7 @@ def test_eigenprojector_identities():
     """sum E_k = I, sum lambda_k E_k = A, E_k E_j = delta_kj E_k, and
     E_k = x_k y_k^T with x_k = V[:, k], y_k^T = V^-1[k, :] of the generator."""
     import workloads as w
-    c = w.config5(6, seed=79, with_basis=True)
+    c = w.differentiation_batch(6, seed=79, with_basis=True)
     for m in range(6):
         a = c["a"][m]
         e = np.array(exact.eigenprojectors(a)).reshape(3, 3, 3)
@@ -301,7 +301,7 @@ def test_matrix_functions_against_scipy():
     symmetric positive definite ones: independent algorithms."""
     import scipy.linalg as sl
     import workloads as w
-    c = w.config5(6, seed=11)
+    c = w.differentiation_batch(6, seed=11)
     for m in range(6):
         a = c["a"][m]
         e = np.array(exact.matrix_function(a, "exp")).reshape(3, 3)
@@ -346,7 +346,7 @@ def test_matrix_function_vjp_against_torch_and_differences():
     h = 1e-20) for exp, log and sqrt."""
     import torch
     import workloads as w
-    c = w.config5(4, seed=14)
+    c = w.differentiation_batch(4, seed=14)
     rng = np.random.default_rng(15)
     for m in range(4):
         a = c["a"][m]

@@ -39,8 +39,8 @@ def _pins(o):
         lambda: pins.test_paper_performance_example(o),
         lambda: pins.test_backward_identities(o),
         lambda: pins.test_ordering_and_spectral_sums(o),
-        lambda: pins.test_within_stability_bounds_well_conditioned(o, "config1"),
-        lambda: pins.test_within_stability_bounds_well_conditioned(o, "config5"),
+        lambda: pins.test_within_stability_bounds_well_conditioned(o, "Haar-similar batch"),
+        lambda: pins.test_within_stability_bounds_well_conditioned(o, "differentiation batch"),
         lambda: pins.test_perturbation_sweep_buckets(o, 1.0, 8.0),
         lambda: pins.test_backward_against_exact_and_eigenvectors(o),
     ]

@@ -73,19 +73,19 @@ def test_printed_r10_sign_breaks_identity(plain_oracle):
     assert differs >= 45
 
 
-@pytest.mark.parametrize("which", ["config1", "config3", "config5"])
+@pytest.mark.parametrize("which", ["Haar-similar batch", "stress tensors", "differentiation batch"])
 def test_within_stability_bounds_well_conditioned(plain_oracle, which):
     """The paper reports its algorithms within the (C = 1) stability bounds for
     well-conditioned eigenbases; on kappa <= 10 the plain implementation stays
     within 8x of them, and a dropped term or a wrong sign would not."""
-    if which == "config1":
-        c = w.config1(300)
+    if which == "Haar-similar batch":
+        c = w.haar_general(300)
         a, kappa = c["a"], c["kappa"]
-    elif which == "config3":
-        c = w.config3(300)
+    elif which == "stress tensors":
+        c = w.stress_tensors(300)
         a, kappa = w.symmetric_to_general(c["s"]), np.ones(300)
     else:
-        c = w.config5(600)
+        c = w.differentiation_batch(600)
         sel = c["kappa"] <= 10
         a, kappa = c["a"][sel], c["kappa"][sel]
     worst = _ratios(plain_oracle, a, kappa)
@@ -100,7 +100,7 @@ def test_perturbation_sweep_buckets(plain_oracle, kappa, factor):
     the eigenbasis condition (Delta reaches about 10x at kappa = 10, and the
     paper reports bound violations for the ill-conditioned U_2), so kappa = 10
     is held to 32x here; kappa = 100 is left to the G2 rule of the GPU tests."""
-    c = w.config2(9 * 60)
+    c = w.perturbation_sweep(9 * 60)
     sel = c["kappa"] == kappa
     worst = _ratios(plain_oracle, c["a"][sel], c["kappa"][sel])
     assert np.all(worst <= factor), worst
@@ -173,7 +173,7 @@ def test_triangular_bitwise_equals_diagonal(plain_oracle):
 def test_symmetric_discriminant_nonnegative(plain_oracle):
     """For symmetric input u = v bit for bit, so the computed Delta is a sum
     of nonnegative terms."""
-    c = w.config3(20000)
+    c = w.stress_tensors(20000)
     a = w.symmetric_to_general(c["s"])
     _, _, _, disc = plain_oracle.invariants(a)
     assert np.all(disc >= 0)
@@ -181,7 +181,7 @@ def test_symmetric_discriminant_nonnegative(plain_oracle):
 
 def test_ordering_and_spectral_sums(plain_oracle):
     """Ascending order; sum of eigenvalues equals I1 within the bound."""
-    c = w.config1(20000)
+    c = w.haar_general(20000)
     lam = plain_oracle.eigvals(c["a"])
     assert np.all(np.diff(lam, axis=1) >= 0)
     tr = c["a"][:, 0] + c["a"][:, 4] + c["a"][:, 8]
@@ -192,7 +192,7 @@ def test_ordering_and_spectral_sums(plain_oracle):
 def test_backward_against_exact_and_eigenvectors(plain_oracle):
     """Eigenprojector backward vs the exact gradient and the eigenvector
     formula y_i x_i^T / (y_i^T x_i) from the generator's basis."""
-    c = w.config5(200, with_basis=True)
+    c = w.differentiation_batch(200, with_basis=True)
     grad = plain_oracle.eigvals_backward(c["a"], c["g"])
     for m in range(0, 200, 10):
         ref = exact.eigvals_vjp(c["a"][m], c["g"][m])
@@ -207,7 +207,7 @@ def test_backward_against_exact_and_eigenvectors(plain_oracle):
 
 def test_backward_identities(plain_oracle):
     """g = 1 -> I and g = lambda -> A^T."""
-    c = w.config5(500)
+    c = w.differentiation_batch(500)
     one = plain_oracle.eigvals_backward(c["a"], np.ones((500, 3)))
     assert np.abs(one - np.eye(3).ravel()).max() < 1e-9
     lam = plain_oracle.eigvals(c["a"])
@@ -218,7 +218,7 @@ def test_backward_identities(plain_oracle):
 
 def test_backward_central_differences(plain_oracle):
     """Central differences (h = 1e-6) of the plain eigenvalues."""
-    c = w.config5(50)
+    c = w.differentiation_batch(50)
     grad = plain_oracle.eigvals_backward(c["a"], c["g"])
     h = 1e-6
     fd = np.zeros_like(grad)
@@ -231,5 +231,5 @@ def test_backward_central_differences(plain_oracle):
 
 
 def test_threads_do_not_change_results(plain_oracle):
-    c = w.config1(5000)
+    c = w.haar_general(5000)
     assert np.array_equal(plain_oracle.eigvals(c["a"], threads=1), plain_oracle.eigvals(c["a"], threads=4))

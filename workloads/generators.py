@@ -34,7 +34,8 @@ SYMMETRIC_ENTRIES = ("A00", "A11", "A22", "A01", "A02", "A12")
 # positions of the symmetric entries inside the 9 row-major entries
 SYMMETRIC_POS = (0, 4, 8, 1, 2, 5)
 
-SEEDS = {1: 2511001, 2: 2511002, 3: 2511003, 4: 2511003, 5: 2511005}
+SEEDS = {"haar_general": 2511001, "perturbation_sweep": 2511002, "stress_tensors": 2511003,
+         "stress_tensors_f32": 2511003, "differentiation_batch": 2511005}
 
 
 # ----------------------------------------------------------------------------
@@ -122,7 +123,7 @@ def _chunks(n, fn, seed, nthreads=None):
 # workloads
 # ----------------------------------------------------------------------------
 
-def config1(n=100_000, seed=SEEDS[1]):
+def haar_general(n=100_000, seed=SEEDS["haar_general"]):
     """General matrices A = V diag(l) V^-1, V Haar orthogonal, l iid U[-1, 1].
     Returns a (n,9), lam (n,3) prescribed spectrum sorted, kappa (n,)."""
     def fn(rng, start, cnt):
@@ -133,11 +134,11 @@ def config1(n=100_000, seed=SEEDS[1]):
     return _chunks(n, fn, seed)
 
 
-CONFIG2_KAPPAS = (1.0, 10.0, 100.0)
-CONFIG2_VARIANTS = ("triple-spread", "double", "near-triple")
+SWEEP_KAPPAS = (1.0, 10.0, 100.0)
+SWEEP_SPECTRA = ("triple-spread", "double", "near-triple")
 
 
-def config2(n=1 << 24, seed=SEEDS[2]):
+def perturbation_sweep(n=1 << 24, seed=SEEDS["perturbation_sweep"]):
     """Perturbation sweep.  Matrix i has variant i mod 3:
     0: D = diag(1, 1+d, 1+2d); 1: D = diag(1, 1, 1+d); 2: D = I + d S with S a
     symmetric matrix of 6 iid N(0,1) entries; and kappa = (1, 10, 100)[(i // 3) mod 3];
@@ -146,7 +147,7 @@ def config2(n=1 << 24, seed=SEEDS[2]):
     def fn(rng, start, cnt):
         idx = np.arange(start, start + cnt)
         variant = idx % 3
-        kappa = np.asarray(CONFIG2_KAPPAS)[(idx // 3) % 3]
+        kappa = np.asarray(SWEEP_KAPPAS)[(idx // 3) % 3]
         delta = 10.0 ** rng.uniform(-16.0, -1.0, cnt)
         s6 = rng.standard_normal((6, cnt))
         v, vi = _basis(rng, cnt, kappa)
@@ -166,7 +167,7 @@ def config2(n=1 << 24, seed=SEEDS[2]):
     return _chunks(n, fn, seed)
 
 
-def config3(n=1 << 27, seed=SEEDS[3]):
+def stress_tensors(n=1 << 27, seed=SEEDS["stress_tensors"]):
     """Symmetric stress-like tensors, (n, 6) in SYMMETRIC_ENTRIES order.
     Half of each chunk has 6 iid N(0,1)*100 entries; the other half is
     p I + d S with p ~ N(0, 100^2), S symmetric with 6 iid N(0,1) entries,
@@ -187,14 +188,14 @@ def config3(n=1 << 27, seed=SEEDS[3]):
     return _chunks(n, fn, seed)
 
 
-def config4(n=1 << 27, seed=SEEDS[4]):
-    """config3 rounded to binary32 (same matrices, same seed)."""
-    out = config3(n, seed)
+def stress_tensors_f32(n=1 << 27, seed=SEEDS["stress_tensors_f32"]):
+    """stress tensors rounded to binary32 (same matrices, same seed)."""
+    out = stress_tensors(n, seed)
     out["s"] = out["s"].astype(np.float32)
     return out
 
 
-def config5(n=1 << 24, seed=SEEDS[5], with_basis=False):
+def differentiation_batch(n=1 << 24, seed=SEEDS["differentiation_batch"], with_basis=False):
     """Differentiation batch: sorted l ~ U[-1, 1] with min gap >= 1e-3
     (rejection sampling), kappa = 10^U(0, 2), upstream gradient g ~ N(0,1)
     (n, 3).  Returns a, g, lam, kappa and, if with_basis, v and vinv (n, 9)."""
