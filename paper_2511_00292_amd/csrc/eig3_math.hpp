@@ -1445,10 +1445,11 @@ __device__ __forceinline__ void matrix_function_backward_general(const Gen &A, c
     const double s00 = (g.d0 + g.d1) * kThird, s11 = (g.d2 - g.d0) * kThird, s22 = -(g.d1 + g.d2) * kThird;
     const double N1[9] = {s00 - m1, A.a10, A.a20, A.a01, s11 - m1, A.a21, A.a02, A.a12, s22 - m1};
     const double M3[9] = {s00 - m3, A.a10, A.a20, A.a01, s11 - m3, A.a21, A.a02, A.a12, s22 - m3};
-    double N2[9], U1[9], U2[9];
-    matmul3(N1, M3, N2);
+    // N1 and M3 are polynomials in X and commute, so N2 = N1 M3 = M3 N1 is
+    // never formed: N2 G = M3 (N1 G) and W1 N1 + W2 N2 = (W1 + W2 M3) N1
+    double U1[9], U2[9];
     matmul3(N1, G, U1);
-    matmul3(N2, G, U2);
+    matmul3(M3, U1, U2);
     double V[9], W1[9], W2[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
@@ -1456,7 +1457,18 @@ __device__ __forceinline__ void matrix_function_backward_general(const Gen &A, c
         W1[e] = fma_(F10, G[e], fma_(F11, U1[e], F21 * U2[e]));
         W2[e] = fma_(F20, G[e], fma_(F21, U1[e], F22 * U2[e]));
     }
-    // grad = V + W1 N1 + W2 N2
+    // T = W1 + W2 M3, grad = V + T N1
+    double T[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double acc = W1[3 * r + c];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                acc = fma_(W2[3 * r + k], M3[3 * k + c], acc);
+            T[3 * r + c] = acc;
+        }
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1464,7 +1476,7 @@ __device__ __forceinline__ void matrix_function_backward_general(const Gen &A, c
             double acc = V[3 * r + c];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                acc = fma_(W1[3 * r + k], N1[3 * k + c], fma_(W2[3 * r + k], N2[3 * k + c], acc));
+                acc = fma_(T[3 * r + k], N1[3 * k + c], acc);
             grad[3 * r + c] = acc;
         }
 }
