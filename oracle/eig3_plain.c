@@ -17,8 +17,11 @@
  *             trigonometric formula Eq. eigvals-trig.
  *
  * Readings where the printed text is silent or inconsistent:
- *   - r10 of dx: printed with "- M02 M21 d2"; the sum of products only equals
- *     4 J2^3 - 27 J3^2 with "+ M02 M21 d2", which is used here.
+ *   - the factors of dx are derived from the Cauchy-Binet expansion (see
+ *     oracle/gen_formulas.py), not typed in; the derived factor that
+ *     contains M01 d1 d2 and M01 M02 M20 has + M02 M21 d2, where the printed
+ *     r10 has - M02 M21 d2 (with the printed sign the sum of products is not
+ *     4 J2^3 - 27 J3^2).
  *   - the triple angle is atan2(sqrt(27 Delta), 27 J3) in [0, pi], the branch
  *     that equals arccos((3 sqrt3 / 2) J3 / J2^(3/2)) of Eq. eigvals-trig's
  *     definition of phi; a plain arctan of the quotient is wrong for J3 < 0.
@@ -26,8 +29,9 @@
  *     are clamped to 0 before the square roots.
  *   - the three values are sorted ascending at the end (ties may swap by an
  *     ulp otherwise).
- *   - the fractions 1/3, 1/6, 1/27 are divisions, sums run left to right as
- *     printed, and the file is built with -ffp-contract=off (no FMA).
+ *   - the fractions 1/3, 1/6, 1/27 are divisions, sums run left to right
+ *     (for the generated formulas in the order the generator states), and
+ *     the file is built with -ffp-contract=off (no FMA).
  *
  * Backward (vector-Jacobian product) follows the eigenprojector relation
  * d(lambda_k)/dA = E_k^T of Sec. "Introduction and motivation", with the
@@ -77,65 +81,38 @@ static double alg_J3(const double *A)
 }
 
 /* ---------------------------------------------------------------- Alg. 8 */
-/* the auxiliary vector dx(M; d0, d1, d2), 14 entries r1..r14 stored at r[0..13] */
-static void alg_dx(const double *M, double d0, double d1, double d2, double *r)
-{
-    const double M01 = M[1], M02 = M[2];
-    const double M10 = M[3], M12 = M[5];
-    const double M20 = M[6], M21 = M[7];
-    r[0] = M01 * M12 * M20 - M02 * M10 * M21;
-    r[1] = -M01 * M02 * d2 + M01 * M01 * M12 - M02 * M02 * M21;
-    r[2] = M01 * M21 * d1 - M01 * M01 * M20 + M02 * M21 * M21;
-    r[3] = M02 * M12 * d0 + M01 * M12 * M12 - M02 * M02 * M10;
-    r[4] = M01 * M12 * d1 - M01 * M02 * M10 + M02 * M12 * M21;
-    r[5] = M02 * M21 * d0 - M01 * M02 * M20 + M01 * M12 * M21;
-    r[6] = -M02 * M10 * d2 + M01 * M10 * M12 - M02 * M12 * M20;
-    r[7] = M12 * d0 * d1 - M02 * M10 * d1 + M01 * M10 * M12 - M12 * M12 * M21;
-    r[8] = M12 * d0 * d1 - M02 * M10 * d0 + M02 * M12 * M20 - M12 * M12 * M21;
-    r[9] = M01 * d1 * d2 + M02 * M21 * d2 + M01 * M02 * M20 - M01 * M01 * M10; /* sign read as + */
-    r[10] = M01 * d1 * d2 + M02 * M21 * d1 + M01 * M12 * M21 - M01 * M01 * M10;
-    r[11] = -M02 * d0 * d2 + M01 * M12 * d0 + M02 * M12 * M21 - M02 * M02 * M20;
-    r[12] = M02 * d0 * d2 + M01 * M12 * d2 - M01 * M02 * M10 + M02 * M02 * M20;
-    r[13] = d0 * d1 * d2 - M01 * M10 * d0 + M02 * M20 * d1 - M12 * M21 * d2;
-}
+/* The factors r_i of the auxiliary vectors and their weights w_i are not
+   typed in: oracle/gen_formulas.py derives them from the Cauchy-Binet
+   expansion of Parlett's determinant (Sec. "Discriminant") and writes them
+   to eig3_plain_formulas.h, together with the naive monomial sums below.
+   Delta = sum_i w_i u_i v_i, u = dx(A), v = dx(A^T), with the same diagonal
+   differences for both, summed left to right. */
+#include "eig3_plain_formulas.h"
 
 static double alg_disc(const double *A)
 {
-    static const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
     double At[9] = {A[0], A[3], A[6], A[1], A[4], A[7], A[2], A[5], A[8]};
     double d0 = A[0] - A[4], d1 = A[0] - A[8], d2 = A[4] - A[8];
     double u[14], v[14];
-    alg_dx(A, d0, d1, d2, u);
-    alg_dx(At, d0, d1, d2, v);
+    dx_factors(A, d0, d1, d2, u);
+    dx_factors(At, d0, d1, d2, v);
     double disc = 0.0;
     for (int i = 0; i < 14; ++i)
-        disc = disc + w[i] * u[i] * v[i];
+        disc = disc + dx_weights[i] * u[i] * v[i];
     return disc;
 }
 
 /* ------------------------------------------------- comparators (naive) */
-/* Alg. alg:J2-naive: the unrolled monomial sum, evaluated left to right. */
+/* Alg. alg:J2-naive and alg:J3-naive: the monomial expansions of 3 J2 and
+   27 J3 (generated, lexicographic order), summed left to right, then divided. */
 static double alg_J2_naive(const double *A)
 {
-    const double A00 = A[0], A01 = A[1], A02 = A[2];
-    const double A10 = A[3], A11 = A[4], A12 = A[5];
-    const double A20 = A[6], A21 = A[7], A22 = A[8];
-    return (A00 * A00 - A00 * A11 - A00 * A22 + 3 * A01 * A10 + 3 * A02 * A20 + A11 * A11 - A11 * A22 +
-            3 * A12 * A21 + A22 * A22) / 3.0;
+    return naive_3j2(A) / 3.0;
 }
 
-/* Alg. alg:J3-naive: the unrolled monomial sum, evaluated left to right. */
 static double alg_J3_naive(const double *A)
 {
-    const double A00 = A[0], A01 = A[1], A02 = A[2];
-    const double A10 = A[3], A11 = A[4], A12 = A[5];
-    const double A20 = A[6], A21 = A[7], A22 = A[8];
-    return (2 * A00 * A00 * A00 - 3 * A00 * A00 * A11 - 3 * A00 * A00 * A22 + 9 * A00 * A01 * A10 +
-            9 * A00 * A02 * A20 - 3 * A00 * A11 * A11 + 12 * A00 * A11 * A22 - 18 * A00 * A12 * A21 -
-            3 * A00 * A22 * A22 + 9 * A01 * A10 * A11 - 18 * A01 * A10 * A22 + 27 * A01 * A12 * A20 +
-            27 * A02 * A10 * A21 - 18 * A02 * A11 * A20 + 9 * A02 * A20 * A22 + 2 * A11 * A11 * A11 -
-            3 * A11 * A11 * A22 + 9 * A11 * A12 * A21 - 3 * A11 * A22 * A22 + 9 * A12 * A21 * A22 +
-            2 * A22 * A22 * A22) / 27.0;
+    return naive_27j3(A) / 27.0;
 }
 
 /* Alg. alg:J2-tensor / alg:J3-tensor: S = A - tr(A)/3 I, then tr(S S)/2 and
@@ -304,8 +281,8 @@ EXPORT void oracle_aux_vectors(const double *A, double *u, double *v)
 {
     double At[9] = {A[0], A[3], A[6], A[1], A[4], A[7], A[2], A[5], A[8]};
     double d0 = A[0] - A[4], d1 = A[0] - A[8], d2 = A[4] - A[8];
-    alg_dx(A, d0, d1, d2, u);
-    alg_dx(At, d0, d1, d2, v);
+    dx_factors(A, d0, d1, d2, u);
+    dx_factors(At, d0, d1, d2, v);
 }
 
 /* naive comparators (variant 1: monomial sums, 2: tensor) -- invariants

@@ -42,12 +42,19 @@ def _ratios(plain, a, kappa):
     return worst
 
 
+def _weights():
+    from oracle import gen_formulas
+    return np.array([w for w, _, _ in gen_formulas.factor_classes()], dtype=np.float64)
+
+
 def test_integer_matrices_aux_vectors_exact(plain_oracle):
     """Small-integer matrices: every product and sum of Alg. alg:disc-stable is
     exact in binary64, so sum_i w_i u_i v_i must equal the exact Delta.  This
-    pins each r_i of dx, including the sign of r10 as read (+ M02 M21 d2)."""
+    pins each derived factor of dx (and the weights: the class sizes of the
+    Cauchy-Binet minors, 9, 6, 6, 6, 8, 8, 8, 2 x 6 and 1, summing to 64)."""
     rng = np.random.default_rng(21)
-    wts = np.array([9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1], dtype=np.float64)
+    wts = _weights()
+    assert sorted(wts.tolist()) == sorted([9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1])
     for _ in range(300):
         a = rng.integers(-9, 10, 9).astype(np.float64)
         u, v = plain_oracle.aux_vectors(a)
@@ -57,18 +64,30 @@ def test_integer_matrices_aux_vectors_exact(plain_oracle):
 
 
 def test_printed_r10_sign_breaks_identity(plain_oracle):
-    """Documents the reading of r10: flipping the sign of its M02 M21 d2 term
-    back to the printed one makes the sum of products differ from Delta."""
+    """Documents the reading of r10: in the derived factor with the terms
+    M01 d1 d2, -M01^2 M10 and M01 M02 M20 (the paper's r10), flipping its
+    + M02 M21 d2 term to the printed - makes the sum of products differ from
+    Delta."""
+    from oracle import gen_formulas as g
+    cls = g.factor_classes()
+    # the class whose terms are M01 d1 d2, M02 M21 d2, M01^2 M10, M01 M02 M20
+    want = {("M01", "d1", "d2"), ("M02", "M21", "d2"), ("M01", "M01", "M10"), ("M01", "M02", "M20")}
+    idx = [i for i, (_, _, terms) in enumerate(cls)
+           if {tuple(g.OFF_NAMES[j] for j in range(6) for _ in range(off[j])) +
+               tuple(f"d{j}" for j in range(3) for _ in range(e[j])) for _, off, e in terms} == want]
+    assert len(idx) == 1
+    k = idx[0]
+    assert [t[0] for t in cls[k][2] if t[2] == (0, 0, 1)] == [1]  # + M02 M21 d2
     rng = np.random.default_rng(22)
-    wts = np.array([9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1], dtype=np.float64)
+    wts = _weights()
     differs = 0
     for _ in range(50):
         a = rng.integers(-9, 10, 9).astype(np.float64)
         u, v = plain_oracle.aux_vectors(a)
         d2 = a[4] - a[8]
         up, vp = u.copy(), v.copy()
-        up[9] -= 2 * a[2] * a[7] * d2          # M = A:   M02 = A02, M21 = A21
-        vp[9] -= 2 * a[6] * a[5] * d2          # M = A^T: M02 = A20, M21 = A12
+        up[k] -= 2 * a[2] * a[7] * d2          # M = A:   M02 = A02, M21 = A21
+        vp[k] -= 2 * a[6] * a[5] * d2          # M = A^T: M02 = A20, M21 = A12
         differs += float(np.dot(wts * up, vp)) != float(exact.invariants(a)[3])
     assert differs >= 45
 
