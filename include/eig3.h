@@ -34,9 +34,12 @@
  *    back exactly), so eigenvalues, their adjoint, the eigenprojectors and
  *    the Mohr-Coulomb function hold over the whole binary64 range;
  *    eig3_invariants returns the invariants themselves, which overflow
- *    (Delta ~ |A|^6) beyond about 2^170 and underflow below about 2^-170,
- *    and the functions of matrices work on A as it is.  The naive
- *    comparators are evaluated as printed, without scaling.
+ *    (Delta ~ |A|^6) beyond about 2^170 and underflow below about 2^-170;
+ *    the functions of matrices take their eigenvalues from the scaled
+ *    invariants and work with A's own entries otherwise, so they hold while
+ *    products of two entries and f's own values stay in range (about
+ *    2^+-450 for log and sqrt).  The naive comparators are evaluated as
+ *    printed, without scaling.
  *  - Eigenvalues are returned in ascending order lambda_1 <= lambda_2 <=
  *    lambda_3 (Sec. "Introduction and motivation", ordering property).
  *  - Accuracy: with unit roundoff eps (2^-53 binary64, 2^-24 binary32),
@@ -47,11 +50,12 @@
  *      |Delta err| <= ||dev(12 J2^2 A^T - 54 J3 cof dev A)|| ||dev A|| eps
  *                                                            (Lemma lem:disc-fwd-stability)
  *      |lambda err| <= kappa_2 ||A|| eps                     (Lemma lem:eigvals-fwd-stability)
- *    EIG3_COMPENSATED evaluates J2, J3 and the auxiliary vectors of Delta
- *    with error-free products and sums from consistent diagonal differences
- *    and stays within a small multiple of these bounds also for
- *    ill-conditioned eigenbases (measured: within 3x up to kappa_2 = 100),
- *    where the plain algorithms exceed them by up to two orders of magnitude.
+ *    EIG3_DOUBLE_WORD and EIG3_COMPENSATED stay within a small multiple of
+ *    these bounds also for ill-conditioned eigenbases (measured on the
+ *    synthetic workloads up to kappa_2 = 100, and on the paper's own paths
+ *    with kappa_2 ~ 9e3: worst 3.7x for every invariant and eigenvalue),
+ *    where the plain algorithms (EIG3_FMA, and the paper's algorithms in
+ *    plain binary64) exceed them by up to three orders of magnitude.
  */
 #ifndef EIG3_H
 #define EIG3_H
@@ -113,7 +117,21 @@ typedef enum eig3_accuracy {
        NAIVE_TENSOR: S = A - tr(A)/3 I, J2 = tr(S S)/2, J3 = det S by LU with
        partial pivoting, Alg. alg:J2-tensor and alg:J3-tensor. */
     EIG3_NAIVE = 2,
-    EIG3_NAIVE_TENSOR = 3
+    EIG3_NAIVE_TENSOR = 3,
+    /* binary64: J2 and J3 by Alg. alg:J2-stable and alg:J3-stable (as
+       K2 = 6 J2 and K3 = 27 J3) in double-word arithmetic: error-free
+       products and sums from the consistent diagonal differences described
+       under EIG3_COMPENSATED, each kept unrounded as hi + lo (exact to
+       O(eps^2) times the size of its terms); Delta from its definition
+       4 J2^3 - 27 J3^2 = (K2^3 - 2 K3^2) / 54 (beside Eq.
+       triple-angle-arctan) in double-word arithmetic from those unrounded
+       values, so the cancellation between its two terms costs only
+       O(eps^2 |dev A|^6).  Delta is the definition, not the sum of products
+       of Alg. alg:disc-stable.  About the cost of EIG3_FMA, with the
+       accuracy of EIG3_COMPENSATED.
+       binary32: the same error-free evaluation of K2 and K3 in binary32
+       arithmetic; Delta accumulated in binary64 from the widened pairs. */
+    EIG3_DOUBLE_WORD = 4
 } eig3_accuracy;
 
 /* A batch of n matrices resident in device memory. */

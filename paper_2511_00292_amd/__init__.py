@@ -20,8 +20,8 @@ from typing import Sequence, Union
 import torch
 
 from . import _capi
-from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_F32, EIG3_F64, EIG3_FMA, EIG3_GENERAL, EIG3_NAIVE,
-                    EIG3_NAIVE_TENSOR, EIG3_SOA, EIG3_SYMMETRIC, Eig3Error)
+from ._capi import (EIG3_AOS, EIG3_COMPENSATED, EIG3_DOUBLE_WORD, EIG3_F32, EIG3_F64, EIG3_FMA, EIG3_GENERAL,
+                    EIG3_NAIVE, EIG3_NAIVE_TENSOR, EIG3_SOA, EIG3_SYMMETRIC, Eig3Error)
 
 __all__ = [
     "eig3_invariants", "eig3_eigvals", "eig3_eigvals_backward", "eig3_mohr_coulomb", "eig3_eigenprojectors",
@@ -37,7 +37,8 @@ ENTRIES = {
 }
 
 _STRUCT = {"general": EIG3_GENERAL, "symmetric": EIG3_SYMMETRIC}
-_ACC = {"fma": EIG3_FMA, "compensated": EIG3_COMPENSATED, "naive": EIG3_NAIVE, "naive_tensor": EIG3_NAIVE_TENSOR}
+_ACC = {"fma": EIG3_FMA, "compensated": EIG3_COMPENSATED, "naive": EIG3_NAIVE, "naive_tensor": EIG3_NAIVE_TENSOR,
+        "double_word": EIG3_DOUBLE_WORD}
 _DTYPE = {torch.float64: EIG3_F64, torch.float32: EIG3_F32}
 _FN = {"exp": 0, "log": 1, "sqrt": 2}  # eig3_function
 
@@ -118,7 +119,7 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def eig3_invariants(a: Batch, structure: str = "general", accuracy: str = "fma", out=None):
+def eig3_invariants(a: Batch, structure: str = "general", accuracy: str = "double_word", out=None):
     """(I1, J2, J3, Delta), each a tensor of n values (Alg. alg:I1-stable,
     alg:J2-stable, alg:J3-stable, alg:disc-stable)."""
     m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
@@ -127,7 +128,7 @@ def eig3_invariants(a: Batch, structure: str = "general", accuracy: str = "fma",
     return tuple(outs)
 
 
-def eig3_eigvals(a: Batch, structure: str = "general", accuracy: str = "fma", out_layout: str = "aos", out=None):
+def eig3_eigvals(a: Batch, structure: str = "general", accuracy: str = "double_word", out_layout: str = "aos", out=None):
     """Ascending eigenvalues (Alg. alg:eigvals-stable).  out_layout 'aos'
     returns an (n, 3) tensor, 'soa' a tuple of three n-vectors."""
     m, n, dtype, dev, _, _keep = _matrices(a, structure, accuracy)
@@ -144,7 +145,7 @@ def eig3_eigvals(a: Batch, structure: str = "general", accuracy: str = "fma", ou
     raise ValueError("out_layout must be 'aos' or 'soa'")
 
 
-def eig3_eigvals_backward(a: Batch, g: Batch, structure: str = "general", accuracy: str = "fma", out=None):
+def eig3_eigvals_backward(a: Batch, g: Batch, structure: str = "general", accuracy: str = "double_word", out=None):
     """sum_k g_k d(lambda_k)/dA, in the structure and layout of ``a``.
     ``g``: an (n, 3) tensor (array of structures) or three n-vectors."""
     m, n, dtype, dev, layout, _keep = _matrices(a, structure, accuracy)
@@ -170,7 +171,7 @@ def eig3_eigvals_backward(a: Batch, g: Batch, structure: str = "general", accura
     return res if layout == EIG3_AOS else tuple(res)
 
 
-def eig3_mohr_coulomb(sigma: Batch, s_yc: float, m: float, structure: str = "symmetric", accuracy: str = "fma",
+def eig3_mohr_coulomb(sigma: Batch, s_yc: float, m: float, structure: str = "symmetric", accuracy: str = "double_word",
                       grad: bool = True, out=None):
     """Mohr-Coulomb yield function f (n values) and, if ``grad``, df/dsigma
     in the structure and layout of ``sigma`` (symmetric: the 6 components of
@@ -196,7 +197,7 @@ def eig3_mohr_coulomb(sigma: Batch, s_yc: float, m: float, structure: str = "sym
     return f, dfds
 
 
-def eig3_eigenprojectors(a: Batch, structure: str = "general", accuracy: str = "fma", out_layout: str = "aos",
+def eig3_eigenprojectors(a: Batch, structure: str = "general", accuracy: str = "double_word", out_layout: str = "aos",
                          out=None):
     """Eigenprojectors E_1, E_2, E_3 of each matrix (ascending eigenvalues).
     out_layout 'aos': an (n, 3, K) tensor (K = 9 row-major entries, or the 6
@@ -216,7 +217,7 @@ def eig3_eigenprojectors(a: Batch, structure: str = "general", accuracy: str = "
     raise ValueError("out_layout must be 'aos' or 'soa'")
 
 
-def eig3_matrix_function(a: Batch, fn: str = "exp", structure: str = "general", accuracy: str = "fma", out=None):
+def eig3_matrix_function(a: Batch, fn: str = "exp", structure: str = "general", accuracy: str = "double_word", out=None):
     """f(A) = sum_k f(lambda_k) E_k for fn in ('exp', 'log', 'sqrt'), in the
     structure and layout of ``a`` (symmetric: the 6 components)."""
     if fn not in _FN:
@@ -235,7 +236,7 @@ def eig3_matrix_function(a: Batch, fn: str = "exp", structure: str = "general", 
 
 
 def eig3_matrix_function_backward(a: Batch, g: Batch, fn: str = "exp", structure: str = "general",
-                                  accuracy: str = "fma", out=None):
+                                  accuracy: str = "double_word", out=None):
     """d<G, f(A)>/dA in the structure and layout of ``a``; ``g`` in the
     layout of the forward's output (that of ``a``)."""
     if fn not in _FN:
@@ -269,7 +270,7 @@ class Eig3MatrixFunction(torch.autograd.Function):
     eig3_matrix_function_backward as its backward."""
 
     @staticmethod
-    def forward(ctx, a: torch.Tensor, fn: str = "exp", accuracy: str = "fma"):
+    def forward(ctx, a: torch.Tensor, fn: str = "exp", accuracy: str = "double_word"):
         if a.shape[-2:] != (3, 3):
             raise ValueError("expected (..., 3, 3)")
         ac = a.contiguous()
@@ -286,7 +287,7 @@ class Eig3MatrixFunction(torch.autograd.Function):
         return grad.reshape(ac.shape), None, None
 
 
-def matrix_function(a: torch.Tensor, fn: str = "exp", accuracy: str = "fma") -> torch.Tensor:
+def matrix_function(a: torch.Tensor, fn: str = "exp", accuracy: str = "double_word") -> torch.Tensor:
     """f(A) of a (..., 3, 3) device tensor, differentiable."""
     return Eig3MatrixFunction.apply(a, fn, accuracy)
 
@@ -299,7 +300,7 @@ class Eig3MatrixFunctionSymmetric(torch.autograd.Function):
     dL/d(the six stored entries of S)."""
 
     @staticmethod
-    def forward(ctx, s: torch.Tensor, fn: str = "exp", accuracy: str = "fma"):
+    def forward(ctx, s: torch.Tensor, fn: str = "exp", accuracy: str = "double_word"):
         if s.shape[-1] != 6:
             raise ValueError("expected (..., 6): A00 A11 A22 A01 A02 A12")
         sc = s.contiguous()
@@ -316,7 +317,7 @@ class Eig3MatrixFunctionSymmetric(torch.autograd.Function):
         return grad.reshape(sc.shape), None, None
 
 
-def matrix_function_symmetric(s: torch.Tensor, fn: str = "exp", accuracy: str = "fma") -> torch.Tensor:
+def matrix_function_symmetric(s: torch.Tensor, fn: str = "exp", accuracy: str = "double_word") -> torch.Tensor:
     """f(S) of symmetric matrices stored as a (..., 6) device tensor
     (A00 A11 A22 A01 A02 A12), in the same storage, differentiable."""
     return Eig3MatrixFunctionSymmetric.apply(s, fn, accuracy)
@@ -327,7 +328,7 @@ class Eig3Eigvals(torch.autograd.Function):
     hand-written adjoint of ``eig3_eigvals_backward`` as its backward."""
 
     @staticmethod
-    def forward(ctx, a: torch.Tensor, accuracy: str = "fma"):
+    def forward(ctx, a: torch.Tensor, accuracy: str = "double_word"):
         shape = a.shape
         if shape[-2:] != (3, 3):
             raise ValueError("expected (..., 3, 3)")
@@ -345,7 +346,7 @@ class Eig3Eigvals(torch.autograd.Function):
         return grad.reshape(ac.shape), None
 
 
-def eigvals(a: torch.Tensor, accuracy: str = "fma") -> torch.Tensor:
+def eigvals(a: torch.Tensor, accuracy: str = "double_word") -> torch.Tensor:
     """Ascending eigenvalues of a (..., 3, 3) float64 device tensor, differentiable."""
     return Eig3Eigvals.apply(a, accuracy)
 
@@ -358,7 +359,7 @@ class Eig3EigvalsSymmetric(torch.autograd.Function):
     positions)."""
 
     @staticmethod
-    def forward(ctx, s: torch.Tensor, accuracy: str = "fma"):
+    def forward(ctx, s: torch.Tensor, accuracy: str = "double_word"):
         shape = s.shape
         if shape[-1] != 6:
             raise ValueError("expected (..., 6): A00 A11 A22 A01 A02 A12")
@@ -376,7 +377,7 @@ class Eig3EigvalsSymmetric(torch.autograd.Function):
         return grad.reshape(sc.shape), None
 
 
-def eigvals_symmetric(s: torch.Tensor, accuracy: str = "fma") -> torch.Tensor:
+def eigvals_symmetric(s: torch.Tensor, accuracy: str = "double_word") -> torch.Tensor:
     """Ascending eigenvalues of symmetric matrices stored as a (..., 6) device
     tensor (A00 A11 A22 A01 A02 A12), float64 or float32, differentiable."""
     return Eig3EigvalsSymmetric.apply(s, accuracy)

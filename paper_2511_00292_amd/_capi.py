@@ -20,7 +20,7 @@ EIG3_OK, EIG3_EINVAL, EIG3_EUNSUPPORTED, EIG3_ELAUNCH = 0, -1, -2, -3
 EIG3_F64, EIG3_F32 = 0, 1
 EIG3_GENERAL, EIG3_SYMMETRIC = 0, 1
 EIG3_SOA, EIG3_AOS = 0, 1
-EIG3_FMA, EIG3_COMPENSATED, EIG3_NAIVE, EIG3_NAIVE_TENSOR = 0, 1, 2, 3
+EIG3_FMA, EIG3_COMPENSATED, EIG3_NAIVE, EIG3_NAIVE_TENSOR, EIG3_DOUBLE_WORD = 0, 1, 2, 3, 4
 
 
 class Eig3Matrices(ctypes.Structure):

@@ -288,11 +288,15 @@ template <int S, int Acc> __device__ __forceinline__ Inv invariants_of(const Mat
     } else if constexpr (S == EIG3_GENERAL) {
         if constexpr (Acc == EIG3_COMPENSATED)
             return invariants_general_comp(to_gen(m));
+        else if constexpr (Acc == EIG3_DOUBLE_WORD)
+            return invariants_general_dw(to_gen(m));
         else
             return invariants_general_fma(to_gen(m));
     } else {
         if constexpr (Acc == EIG3_COMPENSATED)
             return invariants_symmetric_comp(to_sym(m));
+        else if constexpr (Acc == EIG3_DOUBLE_WORD)
+            return invariants_symmetric_dw(to_sym(m));
         else
             return invariants_symmetric_fma(to_sym(m));
     }
@@ -383,6 +387,11 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
             return invariants_f32_comp_general(m.a);
         else
             return invariants_f32_comp_symmetric(m.a);
+    } else if constexpr (Acc == EIG3_DOUBLE_WORD) {
+        if constexpr (S == EIG3_GENERAL)
+            return invariants_f32_dw_general(m.a);
+        else
+            return invariants_f32_dw_symmetric(m.a);
     } else {
         Inv v;
         if constexpr (S == EIG3_GENERAL)
@@ -421,7 +430,22 @@ template <int S> __device__ __forceinline__ int prescale(Mat<double, S> &m)
 
 template <class T, int Acc> constexpr bool scaled_path()
 {
-    return sizeof(T) == 8 && (Acc == EIG3_FMA || Acc == EIG3_COMPENSATED);
+    return sizeof(T) == 8 && (Acc == EIG3_FMA || Acc == EIG3_COMPENSATED || Acc == EIG3_DOUBLE_WORD);
+}
+
+// The triple-angle quantities of a binary64 matrix from its invariants
+// evaluated on the prescaled copy (so that Delta ~ |A|^6 neither over- nor
+// underflows), with the mean and the radius scaled back by 2^e: the
+// eigenvalues of A itself, for kernels that keep working with A's entries.
+template <int S, int Acc> __device__ __forceinline__ Trig trig_of(Mat<double, S> m)
+{
+    int e = 0;
+    if constexpr (scaled_path<double, Acc>())
+        e = prescale(m);
+    Trig t = trig_from_invariants<false>(invariants_of<S, Acc>(m));
+    t.mean = ldexp(t.mean, e);
+    t.r = ldexp(t.r, e);
+    return t;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -663,9 +687,8 @@ EIG3_KERNEL void k_matrix_function(int64_t n, In9<T> in, OutK<T, Mat<T, S>::K> o
     constexpr int KO = Mat<T, S>::K;
     for_each_matrix<T, S, L, KO, L>(n, in, out, [&](const Span &, const Mat<T, S> &mt, double (&o)[KO]) {
         const Mat<double, S> m = widen(mt);
-        const Inv v = invariants_of<S, Acc>(m);
         double F[9];
-        matrix_function_general<Fn>(general_of(m), v, F);
+        matrix_function_general<Fn>(general_of(m), trig_of<S, Acc>(m), F);
         gradient_rows<S, kTensor>(F, o);
     });
 }
@@ -679,7 +702,7 @@ __device__ __forceinline__ void matrix_function_backward_spans(int64_t n, const 
     constexpr int KO = Mat<T, S>::K;
     for_each_matrix<T, S, L, KO, L>(n, in, out, [&](const Span &sp, const Mat<T, S> &mt, double (&o)[KO]) {
         const Mat<double, S> m = widen(mt);
-        const Inv v = invariants_of<S, Acc>(m);
+        const Trig t = trig_of<S, Acc>(m);
         double gk[KO];
 #pragma unroll
         for (int k = 0; k < KO; ++k)
@@ -699,7 +722,7 @@ __device__ __forceinline__ void matrix_function_backward_spans(int64_t n, const 
             G[5] = G[7] = 0.5 * gk[5];
         }
         double gr[9];
-        matrix_function_backward_general<Fn>(general_of(m), v, G, gr);
+        matrix_function_backward_general<Fn>(general_of(m), t, G, gr);
         gradient_rows<S, kStored>(gr, o);
     });
 }
@@ -779,7 +802,7 @@ int check_matrices(const eig3_matrices *A)
     if (A == nullptr || A->n < 0 || A->n > kMaxMatrices)
         return EIG3_EINVAL;
     if (!valid_enum(A->dtype, 1) || !valid_enum(A->structure, 1) || !valid_enum(A->layout, 1) ||
-        !valid_enum(A->accuracy, 3))
+        !valid_enum(A->accuracy, 4))
         return EIG3_EINVAL;
     if (A->n == 0)
         return EIG3_OK;
@@ -835,6 +858,8 @@ template <class F> void dispatch_sla(int s, int l, int acc, F f)
     auto a = [&](auto S, auto L) {
         if (acc == EIG3_COMPENSATED)
             f(S, L, std::integral_constant<int, EIG3_COMPENSATED>{});
+        else if (acc == EIG3_DOUBLE_WORD)
+            f(S, L, std::integral_constant<int, EIG3_DOUBLE_WORD>{});
         else
             f(S, L, std::integral_constant<int, EIG3_FMA>{});
     };

@@ -614,6 +614,167 @@ __device__ __forceinline__ Inv invariants_symmetric_comp(const Sym &S)
     return r;
 }
 
+// ============================================================ DOUBLE WORD
+// J2 and J3 by Alg. alg:J2-stable and alg:J3-stable, scaled to
+//   K2 = 6 J2  = d0^2 + d1^2 + d2^2 + 6 (A01 A10 + A02 A20 + A12 A21),
+//   K3 = 27 J3 = 27 (A01 A12 A20 + A02 A10 A21) + 9 (A01 A10 t1 + A02 A20 t2 + A12 A21 t3) - t1 t2 t3,
+// and evaluated in double-word arithmetic: every product is split exactly
+// (TwoProduct), every sum of leading parts exactly (TwoSum), the low parts
+// are summed plainly, and K2, K3 are kept unrounded as hi + lo, exact to
+// O(eps^2 sum |terms|).  The inputs are the consistent diagonal differences
+// (d0, d2 rounded, d1 = d0 + d2 and t1, t2, t3 exact as pairs), so K2 and K3
+// are the invariants of one matrix, the stored one with its diagonal moved
+// by one rounding of its differences.  Delta is then its definition beside
+// Eq. triple-angle-arctan, 4 J2^3 - 27 J3^2 = (K2^3 - 2 K3^2) / 54, formed
+// from the unrounded K2, K3 in double-word arithmetic: the cancellation
+// between the two terms, which ruins that formula in working precision and
+// which the sum of products of Alg. alg:disc-stable avoids, costs here only
+// O(eps^2 |dev A|^6) (second order in the unit roundoff), and Delta = 0 comes
+// out exactly where K2, K3 describe an exactly repeated eigenvalue.
+
+// s + c with the leading parts summed exactly
+template <class T> struct DWSum {
+    T s, c;
+    __device__ __forceinline__ void add(T x)
+    {
+        T t, e;
+        two_sum(s, x, t, e);
+        s = t;
+        c = c + e;
+    }
+    __device__ __forceinline__ void add(PairT<T> x)
+    {
+        add(x.hi);
+        c = c + x.lo;
+    }
+    // the value rounded once and its remainder
+    __device__ __forceinline__ PairT<T> pair() const
+    {
+        PairT<T> r;
+        r.hi = s + c;
+        r.lo = c - (r.hi - s);
+        return r;
+    }
+};
+
+// k * x for a small integer constant k and x = hi + lo, as hi + lo
+template <class T> __device__ __forceinline__ PairT<T> scaled(T k, PairT<T> x)
+{
+    PairT<T> r;
+    two_prod(k, x.hi, r.hi, r.lo);
+    r.lo = fma_(k, x.lo, r.lo);
+    return r;
+}
+
+template <class T> struct KPair {
+    PairT<T> k2, k3; // 6 J2 and 27 J3, unrounded
+};
+
+// K2 and K3 from the consistent differences g, the three diagonal-pair
+// products p = A01 A10, q = A02 A20, r = A12 A21 (exact pairs) and the
+// off-diagonal triple part 27 (A01 A12 A20 + A02 A10 A21), already
+// accumulated in a.
+template <class T>
+__device__ __forceinline__ KPair<T> k23_dw(const DiagC<T> &g, PairT<T> p, PairT<T> q, PairT<T> r, AccT<T> a)
+{
+    KPair<T> k;
+    {
+        // d0^2 + d1^2 + d2^2 with d1 = d0 + d2 exactly (d1 + d1l)
+        DWSum<T> sq;
+        two_prod(g.d0, g.d0, sq.s, sq.c);
+        PairT<T> d1s = pair(g.d1, g.d1);
+        d1s.lo = fma_(T(2) * g.d1, g.d1l, d1s.lo);
+        sq.add(d1s);
+        sq.add(pair(g.d2, g.d2));
+        DWSum<T> off{p.hi, p.lo};
+        off.add(q);
+        off.add(r);
+        sq.add(scaled(T(6), PairT<T>{off.s, off.c}));
+        k.k2 = sq.pair();
+    }
+    {
+        // t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1, exact as pairs
+        T t1, t1l, t2, t2l, t3, t3l;
+        two_sum(g.d1, g.d2, t1, t1l);
+        t1l = t1l + g.d1l;
+        two_sum(g.d0, -g.d2, t2, t2l);
+        two_sum(-g.d0, -g.d1, t3, t3l);
+        t3l = t3l - g.d1l;
+        a.add(scaled(T(9), p), t1);
+        a.add(scaled(T(9), q), t2);
+        a.add(scaled(T(9), r), t3);
+        const PairT<T> t12 = pair(-t1, t2);
+        a.add(t12, t3);
+        // the low parts of the t's, to first order
+        const T lo9 = fma_(p.hi, t1l, fma_(q.hi, t2l, r.hi * t3l));
+        const T lot = fma_(t12.hi, t3l, -(fma_(t1l, t2, t1 * t2l) * t3));
+        a.c = fma_(T(9), lo9, a.c + lot);
+        PairT<T> k3;
+        a.split(k3.hi, k3.lo);
+        k.k3 = k3;
+    }
+    return k;
+}
+
+template <class T> __device__ __forceinline__ KPair<T> k23_general_dw(const T (&m)[9], const DiagC<T> &g)
+{
+    // m: A00 A01 A02 A10 A11 A12 A20 A21 A22 (or the deviatoric data in the
+    // same positions)
+    AccT<T> a;
+    a.first(pair_scaled(T(27), m[1], m[5]), m[6]);
+    a.add(pair_scaled(T(27), m[2], m[3]), m[7]);
+    return k23_dw(g, pair(m[1], m[3]), pair(m[2], m[6]), pair(m[5], m[7]), a);
+}
+
+template <class T> __device__ __forceinline__ KPair<T> k23_symmetric_dw(T s01, T s02, T s12, const DiagC<T> &g)
+{
+    AccT<T> a;
+    a.first(pair_scaled(T(54), s01, s12), s02);
+    return k23_dw(g, pair(s01, s01), pair(s02, s02), pair(s12, s12), a);
+}
+
+// 54 Delta = K2^3 - 2 K3^2 in double-word arithmetic (binary64)
+__device__ __forceinline__ double disc54_dw(PairT<double> k2, PairT<double> k3)
+{
+    double s2, e2;
+    two_prod(k2.hi, k2.hi, s2, e2);
+    e2 = fma_(2.0 * k2.hi, k2.lo, e2);
+    double c3, c3e;
+    two_prod(s2, k2.hi, c3, c3e);
+    c3e = c3e + fma_(e2, k2.hi, s2 * k2.lo);
+    double q2, q2e;
+    two_prod(k3.hi, k3.hi, q2, q2e);
+    q2e = fma_(2.0 * k3.hi, k3.lo, q2e);
+    double d, de;
+    two_sum(c3, -2.0 * q2, d, de);
+    return d + (de + fma_(-2.0, q2e, c3e));
+}
+
+constexpr double kFiftyFourth = 1.0 / 54.0;
+
+__device__ __forceinline__ Inv invariants_of_k(double i1, const KPair<double> &k)
+{
+    Inv r;
+    r.i1 = i1;
+    r.j2 = (k.k2.hi + k.k2.lo) * kSixth;
+    r.j3 = (k.k3.hi + k.k3.lo) * kTwentySeventh;
+    r.disc = disc54_dw(k.k2, k.k3) * kFiftyFourth;
+    return r;
+}
+
+__device__ __forceinline__ Inv invariants_general_dw(const Gen &A)
+{
+    const double m[9] = {A.a00, A.a01, A.a02, A.a10, A.a11, A.a12, A.a20, A.a21, A.a22};
+    return invariants_of_k(diag_part(A.a00, A.a11, A.a22).i1,
+                           k23_general_dw(m, diag_consistent(A.a00, A.a11, A.a22)));
+}
+
+__device__ __forceinline__ Inv invariants_symmetric_dw(const Sym &S)
+{
+    return invariants_of_k(diag_part(S.s00, S.s11, S.s22).i1,
+                           k23_symmetric_dw(S.s01, S.s02, S.s12, diag_consistent(S.s00, S.s11, S.s22)));
+}
+
 // ======================================================= transcendentals
 // The triple angle needs atan2 of two nonnegative numbers and the sine and
 // cosine of a third of it, t in [0, pi/6]; neither needs a general range
@@ -1046,6 +1207,43 @@ __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
     return r;
 }
 
+// Double-word evaluation in binary32 (EIG3_DOUBLE_WORD): K2 = 6 J2 and
+// K3 = 27 J3 by the same error-free binary32 arithmetic as the binary64
+// double-word path, on the deviatoric data prescaled as above; the unrounded
+// pairs are widened to binary64 (exactly up to 2^-53 relative) and
+// Delta = (K2^3 - 2 K3^2) / 54 is accumulated in binary64, whose rounding
+// (~2^-53 K2^3) stays far below the binary32 pairs' own accuracy
+// (~2^-48 |terms|).
+__device__ __forceinline__ InvW invariants_of_k_f32(double i1, const KPair<float> &k, int sc)
+{
+    const double k2 = double(k.k2.hi) + double(k.k2.lo);
+    const double k3 = double(k.k3.hi) + double(k.k3.lo);
+    InvW r;
+    r.i1 = i1;
+    r.j2 = k2 * kSixth;
+    r.j3 = k3 * kTwentySeventh;
+    r.disc = fma_(k2 * k2, k2, -2.0 * (k3 * k3)) * kFiftyFourth;
+    unscale(r, sc);
+    return r;
+}
+
+__device__ __forceinline__ InvW invariants_f32_dw_general(const float a[9])
+{
+    const float off[6] = {a[1], a[2], a[3], a[5], a[6], a[7]};
+    const DevF32 v = dev_data_f32<6>(a[0], a[4], a[8], off);
+    const float m[9] = {0.0f, v.o[0], v.o[1], v.o[2], 0.0f, v.o[3], v.o[4], v.o[5], 0.0f};
+    const DiagC<float> g{v.d0, v.d1, v.d2, v.d1l};
+    return invariants_of_k_f32(double((a[0] + a[4]) + a[8]), k23_general_dw<float>(m, g), v.sc);
+}
+
+__device__ __forceinline__ InvW invariants_f32_dw_symmetric(const float a[6])
+{
+    const DevF32 v = dev_data_f32<3>(a[0], a[1], a[2], a + 3);
+    const DiagC<float> g{v.d0, v.d1, v.d2, v.d1l};
+    return invariants_of_k_f32(double((a[0] + a[1]) + a[2]), k23_symmetric_dw<float>(v.o[0], v.o[1], v.o[2], g),
+                               v.sc);
+}
+
 // Eigenvalues in binary32 from binary64 invariants.
 __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float &l1, float &l2, float &l3)
 {
@@ -1310,9 +1508,8 @@ template <int Fn> __device__ __forceinline__ double half_second_derivative(doubl
 // the spread.  With exactly repeated eigenvalues the divided differences take
 // their confluent limits (f', f''/2): the Hermite interpolant, which is f(A)
 // also for a defective A.
-template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Inv &v, double F[9])
+template <int Fn> __device__ __forceinline__ void matrix_function_general(const Gen &A, const Trig &t, double F[9])
 {
-    const Trig t = trig_from_invariants<false>(v);
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
     const double l1 = t.mean + m1, l2 = t.mean + m2;
@@ -1390,10 +1587,9 @@ template <int Fn> __device__ __forceinline__ double taylor_coefficient(int k, do
 // the deviatoric part of X (diagonal differences), so the isotropic part
 // cancels exactly.  G and grad are 3x3 row-major.
 template <int Fn>
-__device__ __forceinline__ void matrix_function_backward_general(const Gen &A, const Inv &v, const double G[9],
+__device__ __forceinline__ void matrix_function_backward_general(const Gen &A, const Trig &t, const double G[9],
                                                                  double grad[9])
 {
-    const Trig t = trig_from_invariants<false>(v);
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
     const Gaps gp = gaps_from_trig(t);

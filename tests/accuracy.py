@@ -1,8 +1,10 @@
-"""Error measurement against the exact oracle, shared by the GPU parity tests.
+"""Error measurement against the two oracles, shared by the GPU parity tests.
 
-Gates (forward errors against the exact definitions of oracle/exact.py, bound
-b = the paper's stability bound with C = 1 and Frobenius norms; for
-eigenvalues b = kappa_2(V) ||A|| eps with kappa_2(V) known from the generator):
+O1 is the paper's algorithms in plain binary64 (oracle/eig3_plain.c), O2 the
+exact definitions (oracle/exact.py: exact invariants of the stored matrix,
+80-digit eigenvalues).  Bounds b are the paper's stability bounds with C = 1
+and Frobenius norms; for eigenvalues b = kappa_2(V) ||A|| eps with
+kappa_2(V) known from the generator:
 
   b_I1 = ||A|| eps
   b_J2 = ||S||^2 eps + ||S||^2 eps^2            (S = dev A)
@@ -13,19 +15,21 @@ eigenvalues b = kappa_2(V) ||A|| eps with kappa_2(V) known from the generator):
 The paper's bounds are first order, "+ O(eps^2)"; the second-order term is
 taken as eps^2 ||S||^k with k the degree of the invariant.  It matters only
 where the first-order term vanishes: at an exactly repeated eigenvalue the
-Jacobian of Delta is zero, and an FMA evaluation then returns a Delta of
-order eps^2 ||S||^6 where the exact value is 0.
+Jacobian of Delta is zero, and an evaluation with roundings returns a Delta
+of order eps^2 ||S||^6 where the exact value is 0.
 
-  G1: |x - truth| <= 8 b elementwise            (8x the stability bound)
-  G2: max |x - truth|/b <= 8 + 2 max |x_paper - truth|/b over the bucket,
-      per output: no worse than the paper's own algorithm in plain binary64
-      (oracle/eig3_plain.c) in the worst case, up to a factor 2 for a
-      different rounding order, plus the 8x allowance.
+Gates, each elementwise (every matrix, every output, no pooling):
 
-G1 applies where the paper's algorithms themselves meet their bounds
-(orthogonal and well-conditioned eigenbases, kappa <= 10, and symmetric
-input).  For ill-conditioned eigenbases (kappa = 100) the paper reports
-violations of the J3, Delta and eigenvalue bounds, and G2 applies instead.
+  G1: |x - O1| <= 8 b
+  G2: where G1 misses, |x - O2| <= 8 b + |O1 - O2|: no worse than the paper's
+      own algorithm plus the allowance (the paper reports its J3, Delta and
+      eigenvalue errors above the bounds for ill-conditioned eigenbases, and
+      an evaluation with better rounding may then differ from O1 by more
+      than 8 b)
+  T8: |x - O2| <= 8 b: within 8x the bound of the exact result, whatever O1
+      does.  The claim of the double_word and compensated evaluations at
+      every kappa, and of fma for symmetric input and the eigenvalues at
+      kappa <= 10.
 """
 from __future__ import annotations
 
@@ -95,30 +99,31 @@ def check(err: np.ndarray, bound: np.ndarray, allowance: np.ndarray | None = Non
             f"{(0.0 if allowance is None else allowance[idx]):.3e}")
 
 
-def check_g2(err: np.ndarray, bound: np.ndarray, err_paper: np.ndarray, factor: float = 8.0,
-             what: str = "", pool: bool = False) -> None:
-    """G2: the worst ratio err / bound of x over a bucket is no worse than
-    8 + 2x the worst ratio of the paper's algorithm over the same bucket.
-    Per output column, or, with pool=True, over all columns together (the
-    three eigenvalues of a bucket: at kappa(V) > 10 their worst ratios are
-    heavy-tailed extremes whose position among the three carries no
-    information)."""
-    bound = np.broadcast_to(bound, err.shape)
-    if err.size == 0:
-        return
-    tiny = np.maximum(bound, 1e-300)
-    r = np.where(bound > 0, err / tiny, np.where(err > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
-    rp = np.where(bound > 0, err_paper / tiny, np.where(err_paper > 0, np.inf, 0.0)).reshape(err.shape[0], -1)
-    if pool:
-        r, rp = r.reshape(-1, 1), rp.reshape(-1, 1)
-    lim = factor + 2.0 * rp.max(axis=0)
-    worst = r.max(axis=0)
-    if not np.all(worst <= lim):  # a NaN error fails the gate
-        raise AssertionError(f"{what}: worst ratio {np.round(worst, 2)} exceeds 8 + 2 x paper's "
-                             f"worst {np.round(rp.max(axis=0), 2)}")
+def check_g12(x: np.ndarray, o1: np.ndarray, truth: np.ndarray, bound: np.ndarray, what: str = "",
+              factor: float = 8.0) -> None:
+    """Assert G1 or, where G1 misses, G2, for every element of x."""
+    x, o1, truth = (np.asarray(v, dtype=np.float64) for v in (x, o1, truth))
+    bound = np.broadcast_to(bound, x.shape)
+    g1 = np.abs(x - o1) <= factor * bound
+    g2 = np.abs(x - truth) <= factor * bound + np.abs(o1 - truth)
+    bad = ~(g1 | g2)  # a NaN fails both
+    if bad.any():
+        excess = np.where(bad, (np.abs(x - truth) - np.abs(o1 - truth)) / np.maximum(bound, 1e-300), -np.inf)
+        idx = np.unravel_index(np.argmax(excess), x.shape)
+        raise AssertionError(
+            f"{what}: {int(bad.sum())} of {x.size} values fail G1 and G2; worst at {idx}: "
+            f"|x-O2|={abs(x[idx] - truth[idx]):.3e} |O1-O2|={abs(o1[idx] - truth[idx]):.3e} "
+            f"|x-O1|={abs(x[idx] - o1[idx]):.3e} bound={bound[idx]:.3e}")
+
+
+def g12_failures(x, o1, truth, bound, factor: float = 8.0) -> np.ndarray:
+    """Boolean mask of the elements that fail both G1 and G2."""
+    x, o1, truth = (np.asarray(v, dtype=np.float64) for v in (x, o1, truth))
+    bound = np.broadcast_to(bound, x.shape)
+    return ~((np.abs(x - o1) <= factor * bound) | (np.abs(x - truth) <= factor * bound + np.abs(o1 - truth)))
 
 
 def ratio_summary(err: np.ndarray, bound: np.ndarray) -> dict:
-    r = err / np.maximum(bound, 1e-300)
+    r = np.asarray(err) / np.maximum(np.broadcast_to(bound, np.shape(err)), 1e-300)
     return {"max": float(r.max()) if r.size else 0.0,
             "p9999": float(np.percentile(r, 99.99)) if r.size else 0.0}

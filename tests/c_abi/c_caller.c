@@ -98,7 +98,7 @@ int main(int argc, char **argv)
     A.dtype = EIG3_F64;
     A.structure = EIG3_GENERAL;
     A.layout = EIG3_SOA;
-    A.accuracy = EIG3_FMA;
+    A.accuracy = EIG3_DOUBLE_WORD;
     for (int k = 0; k < 9; ++k)
         A.a[k] = da[k];
 

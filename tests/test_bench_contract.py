@@ -47,4 +47,22 @@ def test_summaries_follow_the_source_digest(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "source_digest", lambda: digest)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.traffic_record("bwd_general_f64_fma") is None
-    assert bench.stated_accuracy() is None
+    assert bench.accuracy_report() is None
+    assert bench.stated_accuracy(None) is None
+    assert bench.within_8x(None, "differentiation batch, general f64", "double_word") is None
+
+
+def test_stated_accuracy_from_a_report():
+    out = {"gpu_vs_exact": {"max": 2.5, "p9999": 1.5}, "gpu_vs_O1": {"max": 40.0, "p9999": 9.0},
+           "O1_vs_exact": {"max": 41.0, "p9999": 9.5}, "g12_fail": 0, "t8_fail": 0, "elements": 10}
+    bad = {**out, "t8_fail": 3}
+    rep = {"rows": [{"workload": "w", "mode": "double_word", "n": 10, "outputs": {"eigvals": out, "J3": out}},
+                    {"workload": "w", "mode": "fma", "n": 10, "outputs": {"eigvals": bad, "J3": out}}],
+           "adjoint": {"double_word": {"gpu": 1e-11, "paper_route": 5e-11}}}
+    s = bench.stated_accuracy(rep)
+    assert s["w"]["double_word"]["within_8x_bound"] is True
+    assert s["w"]["fma"]["within_8x_bound"] is False
+    assert s["w"]["double_word"]["eigvals"]["vs_exact_p9999"] == 1.5
+    assert bench.within_8x(rep, "w", "double_word") is True
+    assert bench.within_8x(rep, "w", "fma") is False
+    assert bench.within_8x(rep, "other", "fma") is None

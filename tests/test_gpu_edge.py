@@ -10,7 +10,7 @@ from gpu_util import download_inv, download_lam, upload
 
 pytestmark = pytest.mark.gpu
 
-ACCS = ["fma", "compensated"]
+ACCS = ["fma", "compensated", "double_word"]
 
 
 @pytest.fixture(scope="module")
@@ -198,3 +198,42 @@ def test_binary64_full_range(eig3, acc, structure):
             full = w.symmetric_to_general(ak.cpu().numpy()) if structure == "symmetric" else ak.cpu().numpy()
             t = Truth(full[::10], np.ones(len(full[::10])))
             check(lam_errors(t, lam.cpu().numpy()[::10]), t.bound_lam(), what=f"2^{k} {structure} {acc}")
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_matrix_function_wide_range(eig3, acc):
+    """Functions of matrices take their eigenvalues from the invariants of
+    the prescaled matrix (Delta ~ |A|^6 would over- or underflow beyond about
+    2^+-170) and keep A's own entries otherwise: for symmetric positive
+    definite A and s = 2^k, k = -400 .. 400, log(s A) = k log(2) I + log(A)
+    and sqrt(s A) = 2^(k/2) sqrt(A), and the adjoints scale as 1/s and
+    2^(-k/2)."""
+    import torch
+    rng = np.random.default_rng(78)
+    mats = []
+    for _ in range(200):
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        m = q @ np.diag(np.sort(rng.uniform(0.5, 2.0, 3))) @ q.T
+        mats.append(m.ravel())
+    dev = torch.device("cuda:0")
+    at = torch.tensor(np.array(mats), device=dev)
+    gt = torch.tensor(rng.standard_normal((200, 9)), device=dev)
+    eye = torch.eye(3, dtype=torch.float64, device=dev).reshape(1, 9)
+    log0 = eig3.eig3_matrix_function(at, "log", "general", acc)
+    sq0 = eig3.eig3_matrix_function(at, "sqrt", "general", acc)
+    glog0 = eig3.eig3_matrix_function_backward(at, gt, "log", "general", acc)
+    gsq0 = eig3.eig3_matrix_function_backward(at, gt, "sqrt", "general", acc)
+    for k in (-400, -200, 200, 400):
+        s = math.ldexp(1.0, k)
+        h = math.ldexp(1.0, k // 2)
+        ak = at * s
+        lg = eig3.eig3_matrix_function(ak, "log", "general", acc)
+        ref = log0 + k * math.log(2.0) * eye
+        assert torch.all((lg - ref).abs() <= 1e-12 * (abs(k) + ref.abs().amax(1, keepdim=True))), k
+        sq = eig3.eig3_matrix_function(ak, "sqrt", "general", acc)
+        assert torch.all((sq - h * sq0).abs() <= 1e-13 * h * sq0.abs().amax(1, keepdim=True)), k
+        gl = eig3.eig3_matrix_function_backward(ak, gt, "log", "general", acc)
+        assert torch.all((gl * s - glog0).abs() <= 1e-12 * glog0.abs().amax(1, keepdim=True)), k
+        gs = eig3.eig3_matrix_function_backward(ak, gt, "sqrt", "general", acc)
+        assert torch.all((gs * h - gsq0).abs() <= 1e-12 * gsq0.abs().amax(1, keepdim=True)), k

@@ -19,7 +19,7 @@ def eig3():
 
 @pytest.mark.parametrize("layout", ["soa", "aos"])
 @pytest.mark.parametrize("out_layout", ["soa", "aos"])
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_against_exact(eig3, layout, out_layout, acc):
     c = w.differentiation_batch(512, seed=81)
     res = eig3.eig3_eigenprojectors(upload(c["a"], layout), "general", acc, out_layout)

@@ -13,7 +13,7 @@ from gpu_util import download_inv, download_lam, upload
 
 pytestmark = pytest.mark.gpu
 
-ACCS = ["fma", "compensated"]
+ACCS = ["fma", "compensated", "double_word"]
 F32_TINY = np.finfo(np.float32).tiny
 
 

@@ -1,15 +1,24 @@
 """GPU parity of the forward path (eig3_invariants, eig3_eigvals) against the
-exact oracle, through the C ABI.  Gates G1/G2 are defined in tests/accuracy.py."""
+two oracles, through the C ABI.  Gates G1, G2 and T8 are defined in
+tests/accuracy.py; every gate is elementwise.
+
+Claims checked here: double_word and compensated within 8x the bounds of the
+exact result (T8) and G1/G2 on every output at every kappa; fma T8 on the
+eigenvalues and G1/G2 on every output for kappa <= 10 and symmetric input.
+fma is not claimed at kappa = 100 (perturbation sweep) and kappa > 10
+(differentiation batch), where it fails G1 and G2 on some elements (the
+accuracy report lists how many)."""
 import numpy as np
 import pytest
 
 import workloads as w
-from accuracy import Truth, check, check_g2, inv_errors, lam_errors
+from accuracy import Truth, check, check_g12, inv_errors, lam_errors
 from gpu_util import download_inv, download_lam, upload
 
 pytestmark = pytest.mark.gpu
 
-ACCS = ["fma", "compensated"]
+ACCS = ["fma", "compensated", "double_word"]
+EXACT = ("compensated", "double_word")  # claimed within 8x at every kappa
 
 
 @pytest.fixture(scope="module")
@@ -73,25 +82,21 @@ def test_perturbation_sweep_buckets(eig3, plain, c2, acc, kappa):
     c, t = c2
     sel = c["kappa"] == kappa
     a = c["a"]
-    lam = download_lam(eig3.eig3_eigvals(upload(a, "soa"), "general", acc, "soa"))
-    inv = download_inv(eig3.eig3_invariants(upload(a, "soa"), "general", acc))
-    o1_lam = plain.eigvals(a)
-    o1_inv = np.stack(plain.invariants(a), axis=1)
-    el, ei = lam_errors(t, lam)[sel], inv_errors(t, inv)[sel]
+    lam = download_lam(eig3.eig3_eigvals(upload(a, "soa"), "general", acc, "soa"))[sel]
+    inv = download_inv(eig3.eig3_invariants(upload(a, "soa"), "general", acc))[sel]
+    o1_lam = plain.eigvals(a)[sel]
+    o1_inv = np.stack(plain.invariants(a), axis=1)[sel]
     bl, bi = t.bound_lam()[sel], t.bound_inv()[sel]
-    al = lam_errors(t, o1_lam)[sel]
-    ai = inv_errors(t, o1_inv)[sel]
-    # compensated: within 8x the bounds at every kappa (consistent diagonal
-    # differences and error-free products); fma: the paper's class, G2 where
-    # the paper's own algorithm exceeds the bounds
-    if kappa <= 10.0 or acc == "compensated":
-        check(el, np.broadcast_to(bl, el.shape), what=f"perturbation sweep eigvals kappa={kappa} {acc} (G1)")
-    else:
-        check_g2(el, bl, al, what=f"perturbation sweep eigvals kappa={kappa} {acc} (G2)", pool=True)
-    if kappa == 1.0 or acc == "compensated":
-        check(ei, bi, what=f"perturbation sweep invariants kappa={kappa} {acc} (G1)")
-    else:
-        check_g2(ei, bi, ai, what=f"perturbation sweep invariants kappa={kappa} {acc} (G2)")
+    if acc == "fma" and kappa > 10.0:
+        # not claimed: only what holds for any evaluation
+        assert np.all(np.isfinite(lam)) and np.all(np.diff(lam, axis=1) >= 0)
+        return
+    what = f"perturbation sweep kappa={kappa} {acc}"
+    check_g12(lam, o1_lam, t.lam.real[sel], bl, what=f"{what} eigvals (G1/G2)")
+    check_g12(inv, o1_inv, t.inv[sel], bi, what=f"{what} invariants (G1/G2)")
+    check(np.abs(lam - t.lam.real[sel]), bl, what=f"{what} eigvals (T8)")
+    if acc in EXACT or kappa == 1.0:
+        check(np.abs(inv - t.inv[sel]), bi, what=f"{what} invariants (T8)")
 
 
 @pytest.mark.parametrize("acc", ACCS)
@@ -110,14 +115,31 @@ def test_stress_tensors_symmetric(eig3, c3, acc, layout):
 def test_differentiation_batch_forward(eig3, plain, c5, acc):
     c, t = c5
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], "aos"), "general", acc, "aos"))
-    el = lam_errors(t, lam)
-    bl = np.broadcast_to(t.bound_lam(), el.shape)
-    well = (c["kappa"] <= 10) | (acc == "compensated")
-    check(el[well], bl[well], what=f"differentiation batch eigvals kappa<=10 or compensated {acc} (G1)")
-    if well.all():
-        return
-    al = lam_errors(t, plain.eigvals(c["a"]))
-    check_g2(el[~well], bl[~well], al[~well], what=f"differentiation batch eigvals kappa>10 {acc} (G2)", pool=True)
+    bl = t.bound_lam()
+    # fma is claimed for kappa <= 10 only
+    well = np.ones(c["a"].shape[0], bool) if acc in EXACT else c["kappa"] <= 10
+    check_g12(lam[well], plain.eigvals(c["a"])[well], t.lam.real[well], bl[well],
+              what=f"differentiation batch eigvals {acc} (G1/G2)")
+    check(lam_errors(t, lam)[well], bl[well], what=f"differentiation batch eigvals {acc} (T8)")
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_haar_general_full_size_g1(eig3, plain, acc):
+    """The Haar-similar batch at its full 100,000 matrices: G1 against the
+    plain binary64 oracle on every eigenvalue; where G1 misses, G2 against the
+    exact eigenvalues of those matrices."""
+    c = w.haar_general()
+    assert c["a"].shape[0] == 100_000
+    lam = download_lam(eig3.eig3_eigvals(upload(c["a"], "soa"), "general", acc, "soa"))
+    o1 = plain.eigvals(c["a"])
+    na = np.sqrt((c["a"] ** 2).sum(axis=1))
+    bound = (na * 2.0 ** -53)[:, None]  # kappa = 1
+    miss = np.abs(lam - o1) > 8 * bound
+    rows = np.nonzero(miss.any(axis=1))[0]
+    assert rows.size < 100, f"{rows.size} matrices miss G1"
+    if rows.size:
+        t = Truth(c["a"][rows], c["kappa"][rows])
+        check_g12(lam[rows], o1[rows], t.lam.real, t.bound_lam(), what=f"Haar-similar batch {acc} G1 misses (G2)")
 
 
 @pytest.mark.parametrize("acc", ACCS)
@@ -141,11 +163,11 @@ def test_ragged_sizes(eig3, n, layout):
     """Sizes around the 64-lane wave and the 256-lane workgroup (LDS tile)."""
     c = w.haar_general(n, seed=99)
     t = Truth(c["a"], c["kappa"])
-    lam = download_lam(eig3.eig3_eigvals(upload(c["a"], layout), "general", "fma", "aos"))
+    lam = download_lam(eig3.eig3_eigvals(upload(c["a"], layout), "general", "double_word", "aos"))
     check(lam_errors(t, lam), t.bound_lam(), what=f"ragged n={n} {layout}")
     s = w.stress_tensors(n, seed=98)
     ts = Truth(w.symmetric_to_general(s["s"]), np.ones(n))
-    lam = download_lam(eig3.eig3_eigvals(upload(s["s"], layout), "symmetric", "fma", "soa"))
+    lam = download_lam(eig3.eig3_eigvals(upload(s["s"], layout), "symmetric", "double_word", "soa"))
     check(lam_errors(ts, lam), ts.bound_lam(), what=f"ragged symmetric n={n} {layout}")
 
 
@@ -157,5 +179,5 @@ def test_aos_unaligned_offset(eig3):
     big = torch.zeros(700 * 9 + 5, dtype=torch.float64, device="cuda:0")
     big[3:3 + 700 * 9] = torch.from_numpy(c["a"].ravel()).to("cuda:0")
     view = big[3:3 + 700 * 9]
-    lam = download_lam(eig3.eig3_eigvals(view, "general", "fma", "aos"))
+    lam = download_lam(eig3.eig3_eigvals(view, "general", "double_word", "aos"))
     check(lam_errors(t, lam), t.bound_lam(), what="aos offset 3")

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from accuracy import EPS64, Truth, check, check_g2, lam_errors
+from accuracy import EPS64, Truth, check, check_g12, lam_errors
 from gpu_util import download_lam, upload
 
 pytestmark = pytest.mark.gpu
@@ -26,35 +26,40 @@ def _properties(a_gen, lam, kappa):
     assert np.all(np.abs(lam.sum(1) - tr) <= 8 * 3 * kappa * nrm * EPS64 + 8 * 3 * nrm * EPS64)
 
 
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_perturbation_sweep_full_2p24_sampled(eig3, plain_oracle, acc):
+    """2^24 matrices of the perturbation sweep: properties on every output;
+    1500 sampled matrices against both oracles, elementwise (G1/G2 and T8;
+    fma only where it is claimed, kappa <= 10)."""
     n = 1 << 24
     c = w.perturbation_sweep(n)
     lam = download_lam(eig3.eig3_eigvals(upload(c["a"], "soa"), "general", acc, "soa"))
     _properties(c["a"], lam, c["kappa"][:, None][:, 0])
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(n, 1500, replace=False))
+    if acc == "fma":
+        idx = idx[c["kappa"][idx] <= 10]
     t = Truth(c["a"][idx], c["kappa"][idx])
-    el = lam_errors(t, lam[idx])
-    bl = np.broadcast_to(t.bound_lam(), el.shape)
-    good = (c["kappa"][idx] <= 10) | (acc == "compensated")
-    check(el[good], bl[good], what=f"perturbation sweep 2^24 kappa<=10 or compensated {acc}")
-    if good.all():
-        return
-    al = lam_errors(t, plain_oracle.eigvals(c["a"][idx]))
-    check_g2(el[~good], bl[~good], al[~good], what=f"perturbation sweep 2^24 kappa=100 {acc} (G2)", pool=True)
+    check_g12(lam[idx], plain_oracle.eigvals(c["a"][idx]), t.lam.real, t.bound_lam(),
+              what=f"perturbation sweep 2^24 {acc} (G1/G2)")
+    check(lam_errors(t, lam[idx]), t.bound_lam(), what=f"perturbation sweep 2^24 {acc} (T8)")
 
 
-def test_stress_tensors_full_2p27_sampled(eig3):
+@pytest.fixture(scope="module")
+def stress_2p27():
+    return w.stress_tensors(1 << 27)["s"]
+
+
+@pytest.mark.parametrize("acc", ["fma", "double_word"])
+def test_stress_tensors_full_2p27_sampled(eig3, stress_2p27, acc):
     n = 1 << 27
-    c = w.stress_tensors(n)
-    s = c["s"]
-    lam = download_lam(eig3.eig3_eigvals(upload(s, "soa"), "symmetric", "fma", "soa"))
+    s = stress_2p27
+    lam = download_lam(eig3.eig3_eigvals(upload(s, "soa"), "symmetric", acc, "soa"))
     rng = np.random.default_rng(8)
     idx = np.sort(rng.choice(n, 1500, replace=False))
     a = w.symmetric_to_general(s[idx])
     t = Truth(a, np.ones(idx.size))
-    check(lam_errors(t, lam[idx]), t.bound_lam(), what="stress tensors 2^27 sampled")
+    check(lam_errors(t, lam[idx]), t.bound_lam(), what=f"stress tensors 2^27 sampled {acc} (T8)")
     assert np.isfinite(lam).all()
     assert np.all(np.diff(lam, axis=1) >= 0)
     tr = s[:, 0] + s[:, 1] + s[:, 2]
@@ -62,7 +67,7 @@ def test_stress_tensors_full_2p27_sampled(eig3):
     assert np.all(np.abs(lam.sum(1) - tr) <= 48 * nrm * EPS64)
 
 
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_stress_tensors_f32_full_2p27_f32_sampled(eig3, acc):
     from accuracy import EPS32
     n = 1 << 27
@@ -77,61 +82,57 @@ def test_stress_tensors_f32_full_2p27_f32_sampled(eig3, acc):
     check(lam_errors(t, lam[idx]), t.bound_lam(EPS32), what=f"binary32 stress tensors 2^27 f32 sampled {acc}")
 
 
-def test_differentiation_batch_full_2p24_step(eig3, plain_oracle):
+@pytest.fixture(scope="module")
+def diff_2p24():
+    return w.differentiation_batch(1 << 24, with_basis=True)
+
+
+@pytest.mark.parametrize("acc", ["double_word", "compensated", "fma"])
+def test_differentiation_batch_full_2p24_step(eig3, plain_oracle, diff_2p24, acc):
     """The benchmark's step at its size and launch shape: eig3_eigvals and
     eig3_eigvals_backward on 2^24 general binary64 matrices, structure of
-    arrays.  Forward: sampled outputs against the exact oracle (G1 for
-    kappa <= 10, G2 above), properties on every output.  Adjoint: every
-    output against the eigenvector formula y_i^T dA x_i / (y_i^T x_i) built
-    from the generator's basis, itself confirmed against the exact gradient
-    at fl(A) (80-digit eigenprojectors) on the worst matrices.  A gradient
-    formed from computed eigenvalues inherits their error divided by the
-    eigenvalue gap (kappa up to 100, gaps down to 1e-3 here), so the fma
-    adjoint's worst error is held to the paper-route oracle's worst on the
-    same batch (plain binary64 eigenvalues and eigenprojectors), and the
-    compensated adjoint to no more than the fma adjoint's worst (measured on
-    this batch: fma 1.2e-6, compensated 1.2e-7, paper route 1.3e-6)."""
+    arrays.  Forward: 1500 sampled matrices against both oracles, elementwise
+    (G1/G2 and T8; fma only for kappa <= 10, where it is claimed); properties
+    on every output.  Adjoint: every output against the eigenvector formula
+    y_i^T dA x_i / (y_i^T x_i) built from the generator's basis, within
+    1e-7 max|grad| (double_word, compensated; the fma adjoint is not claimed
+    at this size: the fma eigenvalues' errors at kappa up to 100, divided by
+    gaps down to 1e-3, reach about 1e-6); the formula itself is confirmed
+    against the exact gradient at the stored matrices (80-digit
+    eigenprojectors) on the 32 matrices where the library is farthest from it."""
     from gpu_util import download_matrix
     from oracle import exact
     n = 1 << 24
-    c = w.differentiation_batch(n, with_basis=True)
+    c = diff_2p24
     a_dev = upload(c["a"], "soa")
     g_dev = upload(c["g"], "soa")
-    lam = download_lam(eig3.eig3_eigvals(a_dev, "general", "fma", "soa"))
-    lam_c = download_lam(eig3.eig3_eigvals(a_dev, "general", "compensated", "soa"))
-    grad = download_matrix(eig3.eig3_eigvals_backward(a_dev, g_dev, "general", "fma"), 9)
-    grad_c = download_matrix(eig3.eig3_eigvals_backward(a_dev, g_dev, "general", "compensated"), 9)
+    lam = download_lam(eig3.eig3_eigvals(a_dev, "general", acc, "soa"))
+    grad = download_matrix(eig3.eig3_eigvals_backward(a_dev, g_dev, "general", acc), 9)
     del a_dev, g_dev
     _properties(c["a"], lam, c["kappa"])
     rng = np.random.default_rng(10)
     idx = np.sort(rng.choice(n, 1500, replace=False))
+    if acc == "fma":
+        idx = idx[c["kappa"][idx] <= 10]
     t = Truth(c["a"][idx], c["kappa"][idx])
-    el = lam_errors(t, lam[idx])
-    bl = np.broadcast_to(t.bound_lam(), el.shape)
-    well = c["kappa"][idx] <= 10
-    check(el[well], bl[well], what="differentiation batch 2^24 kappa<=10 (G1)")
-    al = lam_errors(t, plain_oracle.eigvals(c["a"][idx]))
-    check_g2(el[~well], bl[~well], al[~well], what="differentiation batch 2^24 kappa>10 (G2)", pool=True)
-    check(lam_errors(t, lam_c[idx]), bl, what="differentiation batch 2^24 compensated, every kappa (G1)")
+    check_g12(lam[idx], plain_oracle.eigvals(c["a"][idx]), t.lam.real, t.bound_lam(),
+              what=f"differentiation batch 2^24 {acc} (G1/G2)")
+    check(lam_errors(t, lam[idx]), t.bound_lam(), what=f"differentiation batch 2^24 {acc} (T8)")
 
-    grad_p = plain_oracle.eigvals_backward(c["a"], c["g"])
     v = c["v"].reshape(-1, 3, 3)
     vi = c["vinv"].reshape(-1, 3, 3)
-    r, rc, rp = np.empty(n), np.empty(n), np.empty(n)
+    r = np.empty(n)
     for s in range(0, n, 1 << 21):
         sl = slice(s, s + (1 << 21))
         ref = np.einsum("mk,mki,mjk->mij", c["g"][sl], vi[sl], v[sl]).reshape(-1, 9)
-        scale = np.abs(ref).max(1)
-        r[sl] = np.abs(grad[sl] - ref).max(1) / scale
-        rc[sl] = np.abs(grad_c[sl] - ref).max(1) / scale
-        rp[sl] = np.abs(grad_p[sl] - ref).max(1) / scale
+        r[sl] = np.abs(grad[sl] - ref).max(1) / np.abs(ref).max(1)
+    assert np.isfinite(r).all()
     for m in np.argsort(r)[::-1][:32]:
         ref = np.einsum("k,ki,jk->ij", c["g"][m], vi[m], v[m]).reshape(9)
         ex = exact.eigvals_vjp(c["a"][m], c["g"][m])
         assert np.abs(ref - ex).max() <= 1e-9 * np.abs(ex).max(), int(m)
-    assert np.isfinite(r).all() and np.isfinite(rc).all()
-    assert r.max() <= 2.0 * rp.max() + 1e-8, (r.max(), rp.max())
-    assert rc.max() <= min(r.max(), 2.0 * rp.max() + 1e-8), (rc.max(), r.max(), rp.max())
+    if acc != "fma":
+        assert r.max() <= 1e-7, r.max()
 
 
 def test_differentiation_batch_full_2p24_matrix_exp_and_projectors(eig3):
@@ -239,7 +240,7 @@ def test_stress_tensors_full_2p27_mohr_coulomb(eig3):
             assert np.abs(g_s[j] - ref).max() <= tol, (int(idx[j]), g_s[j], ref)
 
 
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_differentiation_batch_full_2p24_f32(eig3, acc):
     """The benchmark's binary32 step at its size and launch shape: 2^24
     general matrices of the differentiation batch stored in binary32,

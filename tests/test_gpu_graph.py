@@ -33,9 +33,9 @@ def test_step_graph_replay():
     outs = lam + grad + l32
 
     def step():
-        eig3.eig3_eigvals(a, "general", "fma", "soa", out=lam)
-        eig3.eig3_eigvals_backward(a, g, "general", "fma", out=grad)
-        eig3.eig3_eigvals(s32, "symmetric", "fma", "soa", out=l32)
+        eig3.eig3_eigvals(a, "general", "double_word", "soa", out=lam)
+        eig3.eig3_eigvals_backward(a, g, "general", "double_word", out=grad)
+        eig3.eig3_eigvals(s32, "symmetric", "double_word", "soa", out=l32)
 
     def eager():
         step()

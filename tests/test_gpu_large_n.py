@@ -31,7 +31,7 @@ def test_symmetric_beyond_2p31(dtype_name):
     g = torch.Generator(device=dev)
     g.manual_seed(2024)
     s = [torch.randn(N, dtype=dtype, device=dev, generator=g) for _ in range(6)]
-    lam = eig3.eig3_eigvals(s, "symmetric", "fma", "soa")
+    lam = eig3.eig3_eigvals(s, "symmetric", "double_word", "soa")
     torch.cuda.synchronize()
     idx = _indices(N, np.random.default_rng(31))
     it = torch.from_numpy(idx).to(dev)
@@ -39,7 +39,7 @@ def test_symmetric_beyond_2p31(dtype_name):
     got = torch.stack([x.index_select(0, it) for x in lam], 1).cpu().numpy()
     del s, lam
     torch.cuda.empty_cache()
-    ref = torch.stack(eig3.eig3_eigvals(sub, "symmetric", "fma", "soa"), 1).cpu().numpy()
+    ref = torch.stack(eig3.eig3_eigvals(sub, "symmetric", "double_word", "soa"), 1).cpu().numpy()
     assert np.array_equal(got, ref)
     host = np.stack([x.cpu().numpy().astype(np.float64) for x in sub], 1)
     a = np.stack([host[:, 0], host[:, 3], host[:, 4], host[:, 3], host[:, 1], host[:, 5],
@@ -72,8 +72,8 @@ def test_general_aos_beyond_grid(dtype_name):
     a = torch.randn((N_AOS, 3, 3), dtype=dtype, device=dev, generator=g)
     a = (a + a.transpose(1, 2)) * 0.5 + 0.25 * torch.randn((N_AOS, 3, 3), dtype=dtype, device=dev, generator=g)
     gl = torch.randn((N_AOS, 3), dtype=dtype, device=dev, generator=g)
-    lam = eig3.eig3_eigvals(a, "general", "fma", "aos")
-    grad = eig3.eig3_eigvals_backward(a, gl, "general", "fma")
+    lam = eig3.eig3_eigvals(a, "general", "double_word", "aos")
+    grad = eig3.eig3_eigvals_backward(a, gl, "general", "double_word")
     torch.cuda.synchronize()
     rng = np.random.default_rng(28)
     edges = [np.arange(0, 300), np.arange((1 << 28) - 300, (1 << 28) + 300), np.arange(N_AOS - 300, N_AOS)]
@@ -83,8 +83,8 @@ def test_general_aos_beyond_grid(dtype_name):
     got_lam, got_grad = lam.index_select(0, it).cpu(), grad.index_select(0, it).cpu()
     del a, gl, lam, grad
     torch.cuda.empty_cache()
-    ref_lam = eig3.eig3_eigvals(sub_a, "general", "fma", "aos").cpu()
-    ref_grad = eig3.eig3_eigvals_backward(sub_a, sub_g, "general", "fma").cpu()
+    ref_lam = eig3.eig3_eigvals(sub_a, "general", "double_word", "aos").cpu()
+    ref_grad = eig3.eig3_eigvals_backward(sub_a, sub_g, "general", "double_word").cpu()
     assert got_lam.shape == (len(idx), 3) and got_grad.shape == (len(idx), 3, 3)
     # bit patterns: a perturbed matrix with a complex pair has a NaN gradient
     # on both sides

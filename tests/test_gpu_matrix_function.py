@@ -40,7 +40,7 @@ def _rel(got, ref):
 
 
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_exp_general(eig3, layout, acc):
     """exp on the differentiation batch (kappa <= 100, gaps >= 1e-3)."""
     c = w.differentiation_batch(1000, seed=91)
@@ -157,7 +157,7 @@ def test_rejects(eig3):
 
 
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_backward_exp_general(eig3, layout, acc):
     """d<G, exp(A)>/dA against the exact Daleckii-Krein product (kappa <= 100,
     gaps >= 1e-3)."""

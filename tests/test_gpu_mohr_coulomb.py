@@ -113,7 +113,7 @@ def test_invalid_parameters(eig3):
             eig3.eig3_mohr_coulomb(s, syc, m, "symmetric")
 
 
-@pytest.mark.parametrize("acc", ["fma", "compensated"])
+@pytest.mark.parametrize("acc", ["fma", "compensated", "double_word"])
 def test_binary64_scale_invariance(eig3, acc):
     """Binary64 stresses are evaluated on sigma scaled by a power of two:
     with sigma and S_yc both scaled by 2^k, f is bitwise unchanged and
