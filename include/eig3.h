@@ -37,9 +37,10 @@
  *    (Delta ~ |A|^6) beyond about 2^170 and underflow below about 2^-170;
  *    the functions of matrices take their eigenvalues from the scaled
  *    invariants and work with A's own entries otherwise, so they hold while
- *    products of two entries and f's own values stay in range (about
- *    2^+-450 for log and sqrt).  The naive comparators are evaluated as
- *    printed, without scaling.
+ *    products of two entries and f's own values stay in range (log and
+ *    sqrt: about 2^+-450; their adjoints, whose divided differences reach
+ *    the fifth order, about 2^+-200).  The naive comparators are evaluated
+ *    as printed, without scaling.
  *  - Eigenvalues are returned in ascending order lambda_1 <= lambda_2 <=
  *    lambda_3 (Sec. "Introduction and motivation", ordering property).
  *  - Accuracy: with unit roundoff eps (2^-53 binary64, 2^-24 binary32),
@@ -107,8 +108,12 @@ typedef enum eig3_accuracy {
        differences are d0 = A00 - A11 and d2 = A11 - A22 rounded and
        d1 = d0 + d2 carried exactly, so that they are the differences of one
        (perturbed) diagonal.
-       binary32: the same error-free evaluation in binary32 arithmetic, with
-       the products of Delta accumulated in binary64. */
+       binary32: K2 = 6 J2 and K3 = 27 J3 by Alg. alg:J2-stable and
+       alg:J3-stable with binary32 error-free products and sums (the
+       evaluation of EIG3_DOUBLE_WORD in binary32 pairs, on the deviatoric
+       data scaled by a power of two), binary64 only for the Delta
+       accumulation (K2^3 - 2 K3^2)/54 from the widened pairs and for the
+       triple-angle argument. */
     EIG3_COMPENSATED = 1,
     /* Comparators (binary64 eig3_invariants / eig3_eigvals only; other calls
        return EIG3_EUNSUPPORTED): the paper's naive evaluations in plain
@@ -129,8 +134,12 @@ typedef enum eig3_accuracy {
        O(eps^2 |dev A|^6).  Delta is the definition, not the sum of products
        of Alg. alg:disc-stable.  About the cost of EIG3_FMA, with the
        accuracy of EIG3_COMPENSATED.
-       binary32: the same error-free evaluation of K2 and K3 in binary32
-       arithmetic; Delta accumulated in binary64 from the widened pairs. */
+       binary32: the double word of the binary32 data held in one binary64
+       number: entries widened exactly, each product of two of them exact
+       in binary64 (their error-free product), K2, K3 and Delta formed in
+       binary64 (rounding at 2^-53, below a binary32 pair's 2^-48); the
+       cheapest accurate binary32 evaluation on gfx950, where a binary64
+       FMA issues at the rate of a non-packed binary32 one. */
     EIG3_DOUBLE_WORD = 4
 } eig3_accuracy;
 

@@ -24,48 +24,19 @@ using namespace eig3;
 constexpr int kBlock = 256;
 constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 
-// Build-time tuning knobs (defaults are the measured best on MI355X):
-//  EIG3_NONTEMPORAL   1: streaming loads/stores carry the nontemporal hint
-//  EIG3_WAVES_PER_EU  minimum resident waves per SIMD requested from the
-//                     register allocator (0: compiler default)
-#ifndef EIG3_NONTEMPORAL
-#define EIG3_NONTEMPORAL 1
-#endif
-#ifndef EIG3_WAVES_PER_EU
-#define EIG3_WAVES_PER_EU 0
-#endif
-//  EIG3_AOS_DIRECT    1: array-of-structures input is loaded lane by lane
-//                     instead of through the LDS tile
-#ifndef EIG3_AOS_DIRECT
-#define EIG3_AOS_DIRECT 0
-#endif
-//  EIG3_F32_PAIRS     1: binary32 structure-of-arrays eigenvalues take two
-//                     adjacent matrices per lane (8-byte loads and stores)
-#ifndef EIG3_F32_PAIRS
-#define EIG3_F32_PAIRS 1
-#endif
-#if EIG3_WAVES_PER_EU > 0
-#define EIG3_KERNEL __global__ __launch_bounds__(kBlock, EIG3_WAVES_PER_EU)
-#else
 #define EIG3_KERNEL __global__ __launch_bounds__(kBlock)
-#endif
 
+// Streaming accesses: every input is read once and every output written once,
+// so loads and stores carry the nontemporal hint (measured 5-10% faster than
+// without on the binary64 patterns).
 template <class T> __device__ __forceinline__ T ld(const T *p)
 {
-#if EIG3_NONTEMPORAL
     return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
 }
 
 template <class T> __device__ __forceinline__ void st(T v, T *p)
 {
-#if EIG3_NONTEMPORAL
     __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
 }
 
 // The workgroup's span of matrices [first, first + cnt) and this lane's place
@@ -90,7 +61,7 @@ __device__ __forceinline__ Span span_at(int64_t first, int64_t n)
 // raw buffer, 32-bit data format: the gfx9-family descriptor word 3
 constexpr int kBufferWord3 = 0x00020000;
 // cache-policy operand: the nontemporal bit of gfx940-family memory operations
-constexpr int kBufferAux = EIG3_NONTEMPORAL ? 2 : 0;
+constexpr int kBufferAux = 2;
 
 // rows of `per` values: the span's rows of array p
 template <class T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const T *p, const Span &s, int per)
@@ -302,6 +273,27 @@ template <int S, int Acc> __device__ __forceinline__ Inv invariants_of(const Mat
     }
 }
 
+// The triple-angle quantities of m: through K2, K3 and 54 Delta directly in
+// the double-word evaluation, else through the invariants.
+template <int S, int Acc, bool Table>
+__device__ __forceinline__ Trig trig_of_matrix(const Mat<double, S> &m)
+{
+    if constexpr (Acc == EIG3_DOUBLE_WORD) {
+        if constexpr (S == EIG3_GENERAL) {
+            const Gen A = to_gen(m);
+            const double e[9] = {A.a00, A.a01, A.a02, A.a10, A.a11, A.a12, A.a20, A.a21, A.a22};
+            return trig_from_k<Table>(diag_part(A.a00, A.a11, A.a22).i1,
+                                      k23_general_dw(e, diag_consistent(A.a00, A.a11, A.a22)));
+        } else {
+            const Sym y = to_sym(m);
+            return trig_from_k<Table>(diag_part(y.s00, y.s11, y.s22).i1,
+                                      k23_symmetric_dw(y.s01, y.s02, y.s12, diag_consistent(y.s00, y.s11, y.s22)));
+        }
+    } else {
+        return trig_from_invariants<Table>(invariants_of<S, Acc>(m));
+    }
+}
+
 template <class T, int KO>
 __device__ __forceinline__ void store_rows(const OutK<T, KO> &out, int layout, const Span &sp, const double (&o)[KO])
 {
@@ -327,20 +319,13 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, con
 {
     constexpr int K = Mat<T, S>::K;
     const int64_t stride = int64_t(gridDim.x) * kBlock;
-    if constexpr (L == EIG3_SOA || EIG3_AOS_DIRECT) {
+    if constexpr (L == EIG3_SOA) {
         for (int64_t first = int64_t(blockIdx.x) * kBlock; first < n; first += stride) {
             const Span sp = span_at(first, n);
             if (!sp.live())
                 continue;
             Mat<T, S> m;
-            if constexpr (L == EIG3_SOA) {
-                load_soa<T, S>(in, sp, m);
-            } else {
-                // each lane loads its own K consecutive values
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    m.a[k] = span_ld(in.p[0], sp, K, k);
-            }
+            load_soa<T, S>(in, sp, m);
             double o[KO];
             body(sp, m, o);
             store_rows(out, OL, sp, o);
@@ -415,6 +400,10 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
 // back by 2^e; the eigenvalue gradient and the eigenprojectors do not change
 // with the scale.  (Binary32 entries widened to binary64 stay in range
 // without it; the paper's naive comparators are left as printed.)
+// Where the largest entry of every matrix of the wave lies in [2^-64, 2^64)
+// the scaling is skipped: nothing then over- or underflows that the scaled
+// evaluation would keep, and the results are bitwise those of the scaled
+// evaluation (every operation commutes with an exact power of two).
 template <int S> __device__ __forceinline__ int prescale(Mat<double, S> &m)
 {
     double mx = 0.0;
@@ -422,6 +411,8 @@ template <int S> __device__ __forceinline__ int prescale(Mat<double, S> &m)
     for (int k = 0; k < Mat<double, S>::K; ++k)
         mx = fmax(mx, fabs(m.a[k]));
     const int e = __builtin_amdgcn_frexp_exp(mx); // 0 for 0, Inf and NaN: no scaling
+    if (__all(e >= -63 && e <= 64))
+        return 0;
 #pragma unroll
     for (int k = 0; k < Mat<double, S>::K; ++k)
         m.a[k] = ldexp(m.a[k], -e);
@@ -442,7 +433,7 @@ template <int S, int Acc> __device__ __forceinline__ Trig trig_of(Mat<double, S>
     int e = 0;
     if constexpr (scaled_path<double, Acc>())
         e = prescale(m);
-    Trig t = trig_from_invariants<false>(invariants_of<S, Acc>(m));
+    Trig t = trig_of_matrix<S, Acc, false>(m);
     t.mean = ldexp(t.mean, e);
     t.r = ldexp(t.r, e);
     return t;
@@ -468,7 +459,7 @@ EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
         if constexpr (scaled_path<T, Acc>()) {
             Mat<double, S> m = mt;
             const int e = prescale(m);
-            eigvals_from_invariants(invariants_of<S, Acc>(m), o[0], o[1], o[2]);
+            eigvals_from_trig(trig_of_matrix<S, Acc, true>(m), o[0], o[1], o[2]);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 o[k] = ldexp(o[k], e);
@@ -603,8 +594,7 @@ EIG3_KERNEL void k_backward(int64_t n, In9<T> in, G3<T> g, OutK<T, Mat<T, S>::K>
         Mat<double, S> m = widen(mt);
         if constexpr (scaled_path<T, Acc>())
             prescale(m); // the gradient does not change with the scale
-        const Inv v = invariants_of<S, Acc>(m);
-        const Coef c = backward_coefficients(v, g1, g2, g3);
+        const Coef c = backward_coefficients(trig_of_matrix<S, Acc, false>(m), g1, g2, g3);
         double gr[9];
         backward_general(general_of(m), c, gr);
         gradient_rows<S, kStored>(gr, o);
@@ -656,8 +646,7 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
         Mat<double, S> m = widen(mt);
         if constexpr (scaled_path<T, Acc>())
             prescale(m); // the projectors do not change with the scale
-        const Inv v = invariants_of<S, Acc>(m);
-        const Trig t = trig_from_invariants<false>(v);
+        const Trig t = trig_of_matrix<S, Acc, false>(m);
         double E[27];
         eigenprojectors_general(general_of(m), t, E);
 #pragma unroll
@@ -682,7 +671,7 @@ EIG3_KERNEL void k_eigenprojectors(int64_t n, In9<T> in, OutK<T, 3 * Mat<T, S>::
 // binary64 arithmetic for either storage type; the result in the structure
 // and layout of A (symmetric: the 6 components).
 template <class T, int S, int L, int Acc, int Fn>
-EIG3_KERNEL void k_matrix_function(int64_t n, In9<T> in, OutK<T, Mat<T, S>::K> out)
+__device__ __forceinline__ void matrix_function_spans(int64_t n, const In9<T> &in, const OutK<T, Mat<T, S>::K> &out)
 {
     constexpr int KO = Mat<T, S>::K;
     for_each_matrix<T, S, L, KO, L>(n, in, out, [&](const Span &, const Mat<T, S> &mt, double (&o)[KO]) {
@@ -691,6 +680,23 @@ EIG3_KERNEL void k_matrix_function(int64_t n, In9<T> in, OutK<T, Mat<T, S>::K> o
         matrix_function_general<Fn>(general_of(m), trig_of<S, Acc>(m), F);
         gradient_rows<S, kTensor>(F, o);
     });
+}
+
+template <class T, int S, int L, int Acc, int Fn>
+EIG3_KERNEL void k_matrix_function(int64_t n, In9<T> in, OutK<T, Mat<T, S>::K> out)
+{
+    matrix_function_spans<T, S, L, Acc, Fn>(n, in, out);
+}
+
+// The fma and double-word evaluations with at most 168 VGPRs: 3 resident
+// waves per SIMD instead of the 2 that the compiler's default allocation
+// (172 for exp) leaves (measured 18% faster for exp); the compensated
+// evaluation spills at that limit and keeps the default.
+template <class T, int S, int L, int Acc, int Fn>
+EIG3_KERNEL __attribute__((amdgpu_waves_per_eu(3))) void k_matrix_function_w3(int64_t n, In9<T> in,
+                                                                               OutK<T, Mat<T, S>::K> out)
+{
+    matrix_function_spans<T, S, L, Acc, Fn>(n, in, out);
 }
 
 // Vector-Jacobian product of the matrix function: g in the layout of A
@@ -733,15 +739,15 @@ EIG3_KERNEL void k_matrix_function_backward(int64_t n, In9<T> in, In9<T> gin, Ou
     matrix_function_backward_spans<T, S, L, Acc, Fn>(n, in, gin, out);
 }
 
-// The fma evaluation with at most 168 VGPRs, so that 3 waves per SIMD are
-// resident instead of 2 (measured 5-7% faster for exp; the compensated
-// evaluation spills at that limit and keeps the default).
-template <class T, int S, int L, int Fn>
-EIG3_KERNEL __attribute__((amdgpu_waves_per_eu(3))) void k_matrix_function_backward_fma(int64_t n, In9<T> in,
+// The fma and double-word evaluations with at most 168 VGPRs, so that 3 waves
+// per SIMD are resident instead of 2 (measured 5-7% faster for exp; the
+// compensated evaluation spills at that limit and keeps the default).
+template <class T, int S, int L, int Acc, int Fn>
+EIG3_KERNEL __attribute__((amdgpu_waves_per_eu(3))) void k_matrix_function_backward_w3(int64_t n, In9<T> in,
                                                                                         In9<T> gin,
                                                                                         OutK<T, Mat<T, S>::K> out)
 {
-    matrix_function_backward_spans<T, S, L, EIG3_FMA, Fn>(n, in, gin, out);
+    matrix_function_backward_spans<T, S, L, Acc, Fn>(n, in, gin, out);
 }
 
 // ------------------------------------------------------------------- host
@@ -957,15 +963,21 @@ int eig3_matrix_function(const eig3_matrices *A, int32_t fn, void *const out[9],
         dispatch_sla(A->structure, A->layout, A->accuracy, [&](auto S, auto L, auto Acc) {
             constexpr int KO = S.value == EIG3_GENERAL ? 9 : 6;
             const OutK<T, KO> o = out_slots<T, KO>(outs, nout);
+            auto go = [&](auto fnv) {
+                constexpr int F = decltype(fnv)::value;
+                if constexpr (Acc.value == EIG3_COMPENSATED)
+                    hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, F>), grid, block, 0, stream,
+                                       A->n, in, o);
+                else
+                    hipLaunchKernelGGL((k_matrix_function_w3<T, S.value, L.value, Acc.value, F>), grid, block, 0,
+                                       stream, A->n, in, o);
+            };
             if (fn == EIG3_EXP)
-                hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_EXP>), grid, block, 0,
-                                   stream, A->n, in, o);
+                go(std::integral_constant<int, EIG3_EXP>{});
             else if (fn == EIG3_LOG)
-                hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_LOG>), grid, block, 0,
-                                   stream, A->n, in, o);
+                go(std::integral_constant<int, EIG3_LOG>{});
             else
-                hipLaunchKernelGGL((k_matrix_function<T, S.value, L.value, Acc.value, EIG3_SQRT>), grid, block, 0,
-                                   stream, A->n, in, o);
+                go(std::integral_constant<int, EIG3_SQRT>{});
         });
     };
     if (A->dtype == EIG3_F32)
@@ -1017,9 +1029,9 @@ int eig3_matrix_function_backward(const eig3_matrices *A, int32_t fn, const void
             const OutK<T, KO> o = out_slots<T, KO>(outs, np);
             auto go = [&](auto fnv) {
                 constexpr int F = decltype(fnv)::value;
-                if constexpr (Acc.value == EIG3_FMA)
-                    hipLaunchKernelGGL((k_matrix_function_backward_fma<T, S.value, L.value, F>), grid, block, 0,
-                                       stream, A->n, in, gin, o);
+                if constexpr (Acc.value != EIG3_COMPENSATED)
+                    hipLaunchKernelGGL((k_matrix_function_backward_w3<T, S.value, L.value, Acc.value, F>), grid,
+                                       block, 0, stream, A->n, in, gin, o);
                 else
                     hipLaunchKernelGGL((k_matrix_function_backward<T, S.value, L.value, Acc.value, F>), grid,
                                        block, 0, stream, A->n, in, gin, o);
@@ -1097,7 +1109,7 @@ int eig3_eigvals(const eig3_matrices *A, int32_t out_layout, void *const lam[3],
                                    A->n, in, out);
         });
     };
-    if (A->dtype == EIG3_F32 && A->layout == EIG3_SOA && out_layout == EIG3_SOA && EIG3_F32_PAIRS &&
+    if (A->dtype == EIG3_F32 && A->layout == EIG3_SOA && out_layout == EIG3_SOA &&
         all_aligned(A, outs, 8)) {
         const In9<float> in = inputs_of<float>(A);
         const OutK<float, 3> out = out_slots<float, 3>(outs, nout);

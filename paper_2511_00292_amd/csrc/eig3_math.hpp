@@ -922,18 +922,31 @@ constexpr double kSqrt3 = 1.7320508075688772935;
 // max(x, 0) that keeps NaN (fmax would drop it)
 __device__ __forceinline__ double clamp0(double x) { return x < 0.0 ? 0.0 : x; }
 
-template <bool Table = true> __device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
+// From I1, J2 / 3, 27 Delta and 27 J3 (each up to rounding; J2 < 0 and
+// Delta < 0 are clamped to 0).
+template <bool Table> __device__ __forceinline__ Trig trig_core(double i1, double j2_3, double disc27, double j3_27)
 {
     Trig t;
-    const double disc = clamp0(v.disc);
-    const double j2 = clamp0(v.j2);
-    double psi = atan2_nonneg<Table>(sqrt(27.0 * disc), 27.0 * fabs(v.j3));
-    psi = v.j3 == v.j3 ? psi : v.j3; // NaN in J3 reaches the eigenvalues
+    double psi = atan2_nonneg<Table>(sqrt(clamp0(disc27)), fabs(j3_27));
+    psi = j3_27 == j3_27 ? psi : j3_27; // NaN in J3 reaches the eigenvalues
     sincos_sixth<Table>(psi * kThird, t.s, t.c);
-    t.r = sqrt(j2 * kThird);
-    t.mean = v.i1 * kThird;
-    t.neg = v.j3 < 0.0;
+    t.r = sqrt(clamp0(j2_3));
+    t.mean = i1 * kThird;
+    t.neg = j3_27 < 0.0;
     return t;
+}
+
+template <bool Table = true> __device__ __forceinline__ Trig trig_from_invariants(const Inv &v)
+{
+    return trig_core<Table>(v.i1, v.j2 * kThird, 27.0 * v.disc, 27.0 * v.j3);
+}
+
+// The double-word evaluation's K2 = 6 J2, K3 = 27 J3 and 54 Delta give
+// J2 / 3 = K2 / 18, 27 Delta = 54 Delta / 2 and 27 J3 = K3 directly.
+template <bool Table = true> __device__ __forceinline__ Trig trig_from_k(double i1, const KPair<double> &k)
+{
+    constexpr double kEighteenth = 1.0 / 18.0;
+    return trig_core<Table>(i1, (k.k2.hi + k.k2.lo) * kEighteenth, 0.5 * disc54_dw(k.k2, k.k3), k.k3.hi + k.k3.lo);
 }
 
 __device__ __forceinline__ void mu_from_trig(const Trig &t, double &m1, double &m2, double &m3)
@@ -960,14 +973,18 @@ __device__ __forceinline__ Gaps gaps_from_trig(const Trig &t)
     return Gaps{t.neg ? e23p : e12p, e13, t.neg ? e12p : e23p};
 }
 
-__device__ __forceinline__ void eigvals_from_invariants(const Inv &v, double &l1, double &l2, double &l3)
+__device__ __forceinline__ void eigvals_from_trig(const Trig &t, double &l1, double &l2, double &l3)
 {
-    const Trig t = trig_from_invariants(v);
     double m1, m2, m3;
     mu_from_trig(t, m1, m2, m3);
     l1 = t.mean + m1;
     l2 = t.mean + m2;
     l3 = t.mean + m3;
+}
+
+__device__ __forceinline__ void eigvals_from_invariants(const Inv &v, double &l1, double &l2, double &l3)
+{
+    eigvals_from_trig(trig_from_invariants(v), l1, l2, l3);
 }
 
 // ============================================================ comparators
@@ -1059,22 +1076,28 @@ __device__ __forceinline__ Inv invariants_general_tensor(const Gen &A)
 }
 
 // ================================================================ binary32
-// Two evaluations of binary32 batches.
+// Three evaluations of binary32 batches; each forms the triple-angle argument
+// in binary64 (sqrt(27 Delta) and 27 |J3|, rescaled by an exact power of two
+// into binary32 range) and finishes with binary32 arctangent, sine and cosine.
 //
 // Widened (EIG3_FMA): entries are converted to binary64 and the invariants
-// come from the binary64 FMA path above; on gfx950 a binary64 FMA issues at
-// the same rate as a non-packed binary32 one, so this is the cheaper of the
-// two and its invariants carry binary64 accuracy.
+// come from the binary64 FMA path above (the paper's algorithms).
 //
-// Compensated (EIG3_COMPENSATED): binary32 arithmetic throughout, with
-// error-free (FMA TwoProduct + TwoSum) evaluation of the off-diagonal part of
-// J2 (general input), of J3 and of every r_i of dx; the sum of products
-// Delta = sum w_i u_i v_i is accumulated in binary64 from the exact hi + lo
-// pairs, so Delta never underflows in binary32.
+// Double word (EIG3_DOUBLE_WORD): K2 = 6 J2 and K3 = 27 J3 by Alg.
+// alg:J2-stable and alg:J3-stable and Delta = (K2^3 - 2 K3^2) / 54 (the
+// double-word evaluation of the binary64 path) with the double word of the
+// binary32 data held in one binary64 number: the entries are widened
+// exactly, the product of two binary32 numbers is exact in binary64 (it is
+// their error-free product hi + lo), and the remaining products and sums
+// round at 2^-53, below a binary32 pair's 2^-48.  On gfx950 a binary64 FMA
+// issues at the rate of a non-packed binary32 one, so this is the cheapest
+// accurate evaluation.
 //
-// Both form the triple-angle argument in binary64 (sqrt(27 Delta) and
-// 27 |J3|, rescaled by an exact power of two into binary32 range) and finish
-// with binary32 arctangent, sine and cosine.
+// Compensated (EIG3_COMPENSATED): binary32 arithmetic for the invariants:
+// K2 and K3 by the same algorithms with binary32 error-free products
+// (FMA TwoProduct) and sums (TwoSum) on prescaled deviatoric data, kept as
+// unrounded binary32 pairs; binary64 only for the Delta accumulation
+// (K2^3 - 2 K3^2 from the widened pairs) and the angle argument.
 
 struct InvW {
     double i1, j2, j3, disc; // binary64 values of the invariants
@@ -1123,96 +1146,11 @@ __device__ __forceinline__ void unscale(InvW &r, int sc)
     r.disc = ldexp(r.disc, 6 * sc);
 }
 
-__device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
-{
-    const float off[6] = {a[1], a[2], a[3], a[5], a[6], a[7]};
-    const DevF32 v = dev_data_f32<6>(a[0], a[4], a[8], off);
-    const float d0 = v.d0, d1 = v.d1, d2 = v.d2;
-    const float a01 = v.o[0], a02 = v.o[1], a10 = v.o[2], a12 = v.o[3], a20 = v.o[4], a21 = v.o[5];
-    InvW r;
-    r.i1 = double((a[0] + a[4]) + a[8]);
-    {
-        const PairT<float> p01 = pair(a01, a10), p02 = pair(a02, a20), p12 = pair(a12, a21);
-        const float sq = fma_(d0, d0, fma_(d1, d1, d2 * d2)) * (1.0f / 6.0f);
-        float s, e1, t, e2, u, e3;
-        two_sum(p01.hi, p02.hi, s, e1);
-        two_sum(s, p12.hi, t, e2);
-        two_sum(t, sq, u, e3);
-        r.j2 = double(u) + double(((e1 + e2) + e3) + ((p01.lo + p02.lo) + p12.lo));
-    }
-    {
-        const float t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
-        AccT<float> acc;
-        acc.first(pair_scaled(27.0f, a01, a12), a20);
-        acc.add(pair_scaled(27.0f, a02, a10), a21);
-        acc.add(pair_scaled(9.0f, a01, a10), t1);
-        acc.add(pair_scaled(9.0f, a02, a20), t2);
-        acc.add(pair_scaled(9.0f, a12, a21), t3);
-        acc.add(pair(-t1, t2), t3);
-        r.j3 = (double(acc.s) + double(acc.c)) * kTwentySeventh;
-    }
-    {
-        const PairT<float> d0d1 = pair(d0, d1), d1d2 = pair(d1, d2), d0d2 = pair(d0, d2);
-        float uh[14], ul[14], vh[14], vl[14];
-        dx_comp<float>(a01, a02, a10, a12, a20, a21, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul, v.d1l);
-        dx_comp<float>(a10, a20, a01, a21, a02, a12, d0, d1, d2, d0d1, d1d2, d0d2, vh, vl, v.d1l);
-        const double w[14] = {9, 6, 6, 6, 8, 8, 8, 2, 2, 2, 2, 2, 2, 1};
-        double disc = 0.0;
-#pragma unroll
-        for (int i = 13; i >= 0; --i)
-            disc = fma_(w[i] * (double(uh[i]) + double(ul[i])), double(vh[i]) + double(vl[i]), disc);
-        r.disc = disc;
-    }
-    unscale(r, v.sc);
-    return r;
-}
-
-__device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
-{
-    const DevF32 v = dev_data_f32<3>(a[0], a[1], a[2], a + 3);
-    const float d0 = v.d0, d1 = v.d1, d2 = v.d2;
-    const float s01 = v.o[0], s02 = v.o[1], s12 = v.o[2];
-    InvW r;
-    r.i1 = double((a[0] + a[1]) + a[2]);
-    const float q01 = s01 * s01, q02 = s02 * s02, q12 = s12 * s12;
-    // a sum of nonnegative terms: no compensation needed
-    r.j2 = double(fma_(fma_(d0, d0, fma_(d1, d1, d2 * d2)), 1.0f / 6.0f, q01 + (q02 + q12)));
-    {
-        const float t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
-        AccT<float> acc;
-        acc.first(pair_scaled(54.0f, s01, s12), s02);
-        acc.add(pair_scaled(9.0f, s01, s01), t1);
-        acc.add(pair_scaled(9.0f, s02, s02), t2);
-        acc.add(pair_scaled(9.0f, s12, s12), t3);
-        acc.add(pair(-t1, t2), t3);
-        r.j3 = (double(acc.s) + double(acc.c)) * kTwentySeventh;
-    }
-    {
-        const PairT<float> d0d1 = pair(d0, d1), d1d2 = pair(d1, d2), d0d2 = pair(d0, d2);
-        float uh[14], ul[14];
-        dx_comp<float>(s01, s02, s01, s12, s02, s12, d0, d1, d2, d0d1, d1d2, d0d2, uh, ul, v.d1l);
-        // Delta = 14 (u2^2 + u3^2 + u4^2) + 2 (u8^2 + ... + u13^2) + u14^2
-        const double w[14] = {0, 14, 14, 14, 0, 0, 0, 2, 2, 2, 2, 2, 2, 1};
-        double disc = 0.0;
-#pragma unroll
-        for (int i = 13; i >= 0; --i) {
-            if (w[i] == 0.0)
-                continue;
-            const double u = double(uh[i]) + double(ul[i]);
-            disc = fma_(w[i] * u, u, disc);
-        }
-        r.disc = disc;
-    }
-    unscale(r, v.sc);
-    return r;
-}
-
-// Double-word evaluation in binary32 (EIG3_DOUBLE_WORD): K2 = 6 J2 and
-// K3 = 27 J3 by the same error-free binary32 arithmetic as the binary64
-// double-word path, on the deviatoric data prescaled as above; the unrounded
-// pairs are widened to binary64 (exactly up to 2^-53 relative) and
-// Delta = (K2^3 - 2 K3^2) / 54 is accumulated in binary64, whose rounding
-// (~2^-53 K2^3) stays far below the binary32 pairs' own accuracy
+// Binary32 pairs (EIG3_COMPENSATED): K2, K3 from the error-free binary32
+// evaluation of the binary64 double-word path on the prescaled deviatoric
+// data; the unrounded pairs are widened to binary64 (exactly up to 2^-53
+// relative) and Delta = (K2^3 - 2 K3^2) / 54 is accumulated in binary64,
+// whose rounding (~2^-53 K2^3) stays far below the pairs' own accuracy
 // (~2^-48 |terms|).
 __device__ __forceinline__ InvW invariants_of_k_f32(double i1, const KPair<float> &k, int sc)
 {
@@ -1227,7 +1165,7 @@ __device__ __forceinline__ InvW invariants_of_k_f32(double i1, const KPair<float
     return r;
 }
 
-__device__ __forceinline__ InvW invariants_f32_dw_general(const float a[9])
+__device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
 {
     const float off[6] = {a[1], a[2], a[3], a[5], a[6], a[7]};
     const DevF32 v = dev_data_f32<6>(a[0], a[4], a[8], off);
@@ -1236,12 +1174,52 @@ __device__ __forceinline__ InvW invariants_f32_dw_general(const float a[9])
     return invariants_of_k_f32(double((a[0] + a[4]) + a[8]), k23_general_dw<float>(m, g), v.sc);
 }
 
-__device__ __forceinline__ InvW invariants_f32_dw_symmetric(const float a[6])
+__device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
 {
     const DevF32 v = dev_data_f32<3>(a[0], a[1], a[2], a + 3);
     const DiagC<float> g{v.d0, v.d1, v.d2, v.d1l};
     return invariants_of_k_f32(double((a[0] + a[1]) + a[2]), k23_symmetric_dw<float>(v.o[0], v.o[1], v.o[2], g),
                                v.sc);
+}
+
+// Binary64 double word of binary32 data (EIG3_DOUBLE_WORD): the widened
+// differences d0, d2 are exact for binary32 operands of nearby exponents
+// (else rounded once at 2^-53, a backward error) and d1 = d0 + d2 is formed
+// from them, as are the t's; the diagonal-pair products p, q, r of two
+// binary32 numbers are exact; the triple products and the sums round once
+// each at 2^-53.  off3 = A01 A12 A20 + A02 A10 A21.
+__device__ __forceinline__ InvW invariants_k64(double x00, double x11, double x22, double p, double q, double r,
+                                               double off3)
+{
+    const double d0 = x00 - x11, d2 = x11 - x22, d1 = d0 + d2;
+    const double k2 = fma_(d0, d0, fma_(d1, d1, fma_(d2, d2, 6.0 * ((p + q) + r))));
+    const double t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
+    const double k3 = fma_(27.0, off3, fma_(9.0, fma_(p, t1, fma_(q, t2, r * t3)), -(t1 * t2) * t3));
+    InvW v;
+    v.i1 = (x00 + x11) + x22;
+    v.j2 = k2 * kSixth;
+    v.j3 = k3 * kTwentySeventh;
+    v.disc = fma_(k2 * k2, k2, -2.0 * (k3 * k3)) * kFiftyFourth;
+    return v;
+}
+
+__device__ __forceinline__ InvW invariants_f32_dw_general(const float a[9])
+{
+    double x[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        x[k] = a[k];
+    return invariants_k64(x[0], x[4], x[8], x[1] * x[3], x[2] * x[6], x[5] * x[7],
+                          fma_(x[1] * x[5], x[6], x[2] * x[3] * x[7]));
+}
+
+__device__ __forceinline__ InvW invariants_f32_dw_symmetric(const float a[6])
+{
+    double x[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        x[k] = a[k];
+    return invariants_k64(x[0], x[1], x[2], x[3] * x[3], x[4] * x[4], x[5] * x[5], 2.0 * (x[3] * x[4] * x[5]));
 }
 
 // Eigenvalues in binary32 from binary64 invariants.

@@ -1,8 +1,9 @@
 """binary32 storage (EIG3_F32): eigenvalues against the exact oracle at the
 binary32 input widened to binary64, with the binary32 unit roundoff in the
-bounds.  Both evaluations are checked: "fma" (binary64 invariants from the
-widened entries) and "compensated" (binary32 error-free products, binary64
-Delta accumulation)."""
+bounds.  Every evaluation is checked: "fma" (the paper's algorithms in
+binary64 on the widened entries), "double_word" (K2, K3 and Delta from
+them in binary64 on the widened entries) and "compensated" (K2, K3 with
+binary32 error-free products and sums, binary64 Delta accumulation)."""
 import numpy as np
 import pytest
 
