@@ -922,15 +922,33 @@ constexpr double kSqrt3 = 1.7320508075688772935;
 // max(x, 0) that keeps NaN (fmax would drop it)
 __device__ __forceinline__ double clamp0(double x) { return x < 0.0 ? 0.0 : x; }
 
+// Square root of x >= 0 (NaN propagates): the hardware reciprocal square
+// root (relative error about 2^-23, denormals supported) refined by one
+// Goldschmidt step and two Newton corrections of the root, within an ulp.
+// The library's own sequence also rescales tiny and huge operands and fixes
+// up 0 and Inf; here only 0 needs it (rsq(0) = Inf), the operands being the
+// scaled matrix's J2 / 3 and 27 Delta.
+__device__ __forceinline__ double sqrt_nonneg(double x)
+{
+    const double r = __builtin_amdgcn_rsq(x);
+    double g = x * r, h = 0.5 * r;
+    const double e = fma_(-h, g, 0.5);
+    g = fma_(g, e, g);
+    h = fma_(h, e, h);
+    g = fma_(fma_(-g, g, x), h, g);
+    g = fma_(fma_(-g, g, x), h, g);
+    return x == 0.0 ? x : g;
+}
+
 // From I1, J2 / 3, 27 Delta and 27 J3 (each up to rounding; J2 < 0 and
 // Delta < 0 are clamped to 0).
 template <bool Table> __device__ __forceinline__ Trig trig_core(double i1, double j2_3, double disc27, double j3_27)
 {
     Trig t;
-    double psi = atan2_nonneg<Table>(sqrt(clamp0(disc27)), fabs(j3_27));
+    double psi = atan2_nonneg<Table>(sqrt_nonneg(clamp0(disc27)), fabs(j3_27));
     psi = j3_27 == j3_27 ? psi : j3_27; // NaN in J3 reaches the eigenvalues
     sincos_sixth<Table>(psi * kThird, t.s, t.c);
-    t.r = sqrt(clamp0(j2_3));
+    t.r = sqrt_nonneg(clamp0(j2_3));
     t.mean = i1 * kThird;
     t.neg = j3_27 < 0.0;
     return t;

@@ -96,6 +96,17 @@ def test_accuracy_report(plain_oracle):
             general(f"perturbation sweep {names[v]} kappa={kappa:g}, general f64", cb["a"][sel], kappa)
     c5 = w.differentiation_batch(1500, seed=15)
     general("differentiation batch, general f64", c5["a"], c5["kappa"])
+    # the same batch stored in binary32 (eigenvalues; bounds with eps = 2^-24
+    # at the stored binary32 matrices)
+    a32 = c5["a"].astype(np.float32)
+    a32w = a32.astype(np.float64)
+    t32 = Truth(a32w, c5["kappa"])
+    o1_inv = np.stack(plain_oracle.invariants(a32w), axis=1)
+    o1_lam = plain_oracle.eigvals(a32w)
+    for acc in MODES:
+        lam = download_lam(eig3.eig3_eigvals(upload(a32, "soa"), "general", acc, "soa"))
+        rep["rows"].append({"workload": "binary32 differentiation batch, general f32", "mode": acc, "n": 1500,
+                            "outputs": _outputs(None, lam, o1_inv, o1_lam, t32, EPS32)})
     # symmetric stress tensors in binary64 and in binary32 (eigenvalues and
     # invariants through the symmetric kernels)
     c3 = w.stress_tensors(1500, seed=14)
