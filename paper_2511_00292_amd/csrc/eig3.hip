@@ -365,18 +365,28 @@ __device__ __forceinline__ void for_each_matrix(int64_t n, const In9<T> &in, con
     }
 }
 
-template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Mat<float, S> &m)
+// binary32 data: K2, K3 and 54 Delta of the double-word and compensated
+// evaluations
+template <int S, int Acc> __device__ __forceinline__ KW kw_of(const Mat<float, S> &m)
 {
+    static_assert(Acc == EIG3_COMPENSATED || Acc == EIG3_DOUBLE_WORD, "K route");
     if constexpr (Acc == EIG3_COMPENSATED) {
         if constexpr (S == EIG3_GENERAL)
-            return invariants_f32_comp_general(m.a);
+            return kw_f32_comp_general(m.a);
         else
-            return invariants_f32_comp_symmetric(m.a);
-    } else if constexpr (Acc == EIG3_DOUBLE_WORD) {
+            return kw_f32_comp_symmetric(m.a);
+    } else {
         if constexpr (S == EIG3_GENERAL)
-            return invariants_f32_dw_general(m.a);
+            return kw_f32_dw_general(m.a);
         else
-            return invariants_f32_dw_symmetric(m.a);
+            return kw_f32_dw_symmetric(m.a);
+    }
+}
+
+template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Mat<float, S> &m)
+{
+    if constexpr (Acc == EIG3_COMPENSATED || Acc == EIG3_DOUBLE_WORD) {
+        return invariants_of_kw(kw_of<S, Acc>(m));
     } else {
         Inv v;
         if constexpr (S == EIG3_GENERAL)
@@ -388,6 +398,15 @@ template <int S, int Acc> __device__ __forceinline__ InvW invariants_of(const Ma
                 Sym{double(m.a[0]), double(m.a[1]), double(m.a[2]), double(m.a[3]), double(m.a[4]), double(m.a[5])});
         return InvW{v.i1, v.j2, v.j3, v.disc};
     }
+}
+
+// the arguments of the binary32 eigenvalue tail
+template <int S, int Acc> __device__ __forceinline__ TrigArgW f32_args_of(const Mat<float, S> &m)
+{
+    if constexpr (Acc == EIG3_COMPENSATED || Acc == EIG3_DOUBLE_WORD)
+        return trig_args_of_kw(kw_of<S, Acc>(m));
+    else
+        return trig_args_of_invariants(invariants_of<S, Acc>(m));
 }
 
 // Binary64 batches are evaluated on A 2^-e, 2^e the binade of A's largest
@@ -466,9 +485,8 @@ EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
         } else if constexpr (sizeof(T) == 8) {
             eigvals_from_invariants(invariants_of<S, Acc>(mt), o[0], o[1], o[2]);
         } else {
-            const auto v = invariants_of<S, Acc>(mt);
             float l1, l2, l3;
-            eigvals_f32_from_invariants(v, l1, l2, l3);
+            eigvals_f32_from_args(f32_args_of<S, Acc>(mt), l1, l2, l3);
             o[0] = l1;
             o[1] = l2;
             o[2] = l3;
@@ -484,7 +502,7 @@ EIG3_KERNEL void k_eigvals(int64_t n, In9<T> in, OutK<T, 3> out)
 // (Only launched when every array is 8-byte aligned.)
 template <int S, int Acc> __device__ __forceinline__ void eigvals_f32(const Mat<float, S> &m, float (&l)[3])
 {
-    eigvals_f32_from_invariants(invariants_of<S, Acc>(m), l[0], l[1], l[2]);
+    eigvals_f32_from_args(f32_args_of<S, Acc>(m), l[0], l[1], l[2]);
 }
 
 template <int S, int Acc> EIG3_KERNEL void k_eigvals_f32x2(int64_t n, In9<float> in, OutK<float, 3> out)

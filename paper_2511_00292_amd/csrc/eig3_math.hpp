@@ -1097,6 +1097,8 @@ __device__ __forceinline__ Inv invariants_general_tensor(const Gen &A)
 // Three evaluations of binary32 batches; each forms the triple-angle argument
 // in binary64 (sqrt(27 Delta) and 27 |J3|, rescaled by an exact power of two
 // into binary32 range) and finishes with binary32 arctangent, sine and cosine.
+// The double-word and compensated evaluations hand K2, K3 and 54 Delta to
+// that tail directly (J2 / 3 = K2 / 18, 27 Delta = 54 Delta / 2, 27 J3 = K3).
 //
 // Widened (EIG3_FMA): entries are converted to binary64 and the invariants
 // come from the binary64 FMA path above (the paper's algorithms).
@@ -1157,47 +1159,55 @@ template <int KO> __device__ __forceinline__ DevF32 dev_data_f32(float a00, floa
     return v;
 }
 
-__device__ __forceinline__ void unscale(InvW &r, int sc)
+// I1, K2 = 6 J2, K3 = 27 J3 and 54 Delta in binary64
+struct KW {
+    double i1, k2, k3, d54;
+};
+
+__device__ __forceinline__ InvW invariants_of_kw(const KW &k)
 {
-    r.j2 = ldexp(r.j2, 2 * sc);
-    r.j3 = ldexp(r.j3, 3 * sc);
-    r.disc = ldexp(r.disc, 6 * sc);
+    InvW r;
+    r.i1 = k.i1;
+    r.j2 = k.k2 * kSixth;
+    r.j3 = k.k3 * kTwentySeventh;
+    r.disc = k.d54 * kFiftyFourth;
+    return r;
 }
 
 // Binary32 pairs (EIG3_COMPENSATED): K2, K3 from the error-free binary32
 // evaluation of the binary64 double-word path on the prescaled deviatoric
 // data; the unrounded pairs are widened to binary64 (exactly up to 2^-53
-// relative) and Delta = (K2^3 - 2 K3^2) / 54 is accumulated in binary64,
-// whose rounding (~2^-53 K2^3) stays far below the pairs' own accuracy
-// (~2^-48 |terms|).
-__device__ __forceinline__ InvW invariants_of_k_f32(double i1, const KPair<float> &k, int sc)
+// relative) and 54 Delta = K2^3 - 2 K3^2 is accumulated in binary64, whose
+// rounding (~2^-53 K2^3) stays far below the pairs' own accuracy (~2^-48
+// |terms|).  Scaled back exactly (K2 by 2^2s, K3 by 2^3s, Delta by 2^6s;
+// binary32 data keep every one of them a normal binary64 number).
+__device__ __forceinline__ KW kw_of_f32_pairs(double i1, const KPair<float> &k, int sc)
 {
     const double k2 = double(k.k2.hi) + double(k.k2.lo);
     const double k3 = double(k.k3.hi) + double(k.k3.lo);
-    InvW r;
+    KW r;
     r.i1 = i1;
-    r.j2 = k2 * kSixth;
-    r.j3 = k3 * kTwentySeventh;
-    r.disc = fma_(k2 * k2, k2, -2.0 * (k3 * k3)) * kFiftyFourth;
-    unscale(r, sc);
+    r.k2 = ldexp(k2, 2 * sc);
+    r.k3 = ldexp(k3, 3 * sc);
+    r.d54 = ldexp(fma_(k2 * k2, k2, -2.0 * (k3 * k3)), 6 * sc);
     return r;
 }
 
-__device__ __forceinline__ InvW invariants_f32_comp_general(const float a[9])
+__device__ __forceinline__ KW kw_f32_comp_general(const float a[9])
 {
     const float off[6] = {a[1], a[2], a[3], a[5], a[6], a[7]};
     const DevF32 v = dev_data_f32<6>(a[0], a[4], a[8], off);
     const float m[9] = {0.0f, v.o[0], v.o[1], v.o[2], 0.0f, v.o[3], v.o[4], v.o[5], 0.0f};
     const DiagC<float> g{v.d0, v.d1, v.d2, v.d1l};
-    return invariants_of_k_f32(double((a[0] + a[4]) + a[8]), k23_general_dw<float>(m, g), v.sc);
+    return kw_of_f32_pairs(double((a[0] + a[4]) + a[8]), k23_general_dw<float>(m, g), v.sc);
 }
 
-__device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
+__device__ __forceinline__ KW kw_f32_comp_symmetric(const float a[6])
 {
     const DevF32 v = dev_data_f32<3>(a[0], a[1], a[2], a + 3);
     const DiagC<float> g{v.d0, v.d1, v.d2, v.d1l};
-    return invariants_of_k_f32(double((a[0] + a[1]) + a[2]), k23_symmetric_dw<float>(v.o[0], v.o[1], v.o[2], g),
-                               v.sc);
+    return kw_of_f32_pairs(double((a[0] + a[1]) + a[2]), k23_symmetric_dw<float>(v.o[0], v.o[1], v.o[2], g),
+                           v.sc);
 }
 
 // Binary64 double word of binary32 data (EIG3_DOUBLE_WORD): the widened
@@ -1206,42 +1216,60 @@ __device__ __forceinline__ InvW invariants_f32_comp_symmetric(const float a[6])
 // from them, as are the t's; the diagonal-pair products p, q, r of two
 // binary32 numbers are exact; the triple products and the sums round once
 // each at 2^-53.  off3 = A01 A12 A20 + A02 A10 A21.
-__device__ __forceinline__ InvW invariants_k64(double x00, double x11, double x22, double p, double q, double r,
-                                               double off3)
+__device__ __forceinline__ KW kw_k64(double x00, double x11, double x22, double p, double q, double r, double off3)
 {
     const double d0 = x00 - x11, d2 = x11 - x22, d1 = d0 + d2;
     const double k2 = fma_(d0, d0, fma_(d1, d1, fma_(d2, d2, 6.0 * ((p + q) + r))));
     const double t1 = d1 + d2, t2 = d0 - d2, t3 = -d0 - d1;
     const double k3 = fma_(27.0, off3, fma_(9.0, fma_(p, t1, fma_(q, t2, r * t3)), -(t1 * t2) * t3));
-    InvW v;
+    KW v;
     v.i1 = (x00 + x11) + x22;
-    v.j2 = k2 * kSixth;
-    v.j3 = k3 * kTwentySeventh;
-    v.disc = fma_(k2 * k2, k2, -2.0 * (k3 * k3)) * kFiftyFourth;
+    v.k2 = k2;
+    v.k3 = k3;
+    v.d54 = fma_(k2 * k2, k2, -2.0 * (k3 * k3));
     return v;
 }
 
-__device__ __forceinline__ InvW invariants_f32_dw_general(const float a[9])
+__device__ __forceinline__ KW kw_f32_dw_general(const float a[9])
 {
     double x[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k)
         x[k] = a[k];
-    return invariants_k64(x[0], x[4], x[8], x[1] * x[3], x[2] * x[6], x[5] * x[7],
-                          fma_(x[1] * x[5], x[6], x[2] * x[3] * x[7]));
+    return kw_k64(x[0], x[4], x[8], x[1] * x[3], x[2] * x[6], x[5] * x[7], fma_(x[1] * x[5], x[6], x[2] * x[3] * x[7]));
 }
 
-__device__ __forceinline__ InvW invariants_f32_dw_symmetric(const float a[6])
+__device__ __forceinline__ KW kw_f32_dw_symmetric(const float a[6])
 {
     double x[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         x[k] = a[k];
-    return invariants_k64(x[0], x[1], x[2], x[3] * x[3], x[4] * x[4], x[5] * x[5], 2.0 * (x[3] * x[4] * x[5]));
+    return kw_k64(x[0], x[1], x[2], x[3] * x[3], x[4] * x[4], x[5] * x[5], 2.0 * (x[3] * x[4] * x[5]));
 }
 
-// Eigenvalues in binary32 from binary64 invariants.
-__device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float &l1, float &l2, float &l3)
+// The binary64 arguments of the binary32 eigenvalue tail: I1, J2 / 3,
+// 27 Delta and 27 J3 (the operands of Eq. triple-angle-arctan and of the
+// radius in Eq. eigvals-trig).
+struct TrigArgW {
+    double i1, j2_3, disc27, j3_27;
+};
+
+__device__ __forceinline__ TrigArgW trig_args_of_invariants(const InvW &v)
+{
+    return TrigArgW{v.i1, v.j2 * kThird, 27.0 * v.disc, 27.0 * v.j3};
+}
+
+// from K2, K3 and 54 Delta: J2 / 3 = K2 / 18 in one rounding, 27 Delta =
+// 54 Delta / 2 and 27 J3 = K3 exactly
+__device__ __forceinline__ TrigArgW trig_args_of_kw(const KW &k)
+{
+    constexpr double kEighteenth = 1.0 / 18.0;
+    return TrigArgW{k.i1, k.k2 * kEighteenth, 0.5 * k.d54, k.k3};
+}
+
+// Eigenvalues in binary32 from the binary64 arguments.
+__device__ __forceinline__ void eigvals_f32_from_args(const TrigArgW &v, float &l1, float &l2, float &l3)
 {
     // The square roots sqrt(27 Delta) and r = sqrt(J2 / 3) are taken by the
     // hardware binary64 square root, an approximation with relative error
@@ -1253,21 +1281,21 @@ __device__ __forceinline__ void eigvals_f32_from_invariants(const InvW &v, float
     // (NaN in J2 or Delta comes only from NaN or Inf entries, which make J3
     // NaN too; the J3 test below carries it to the output, so plain max
     // clamps suffice here)
-    const double y = __builtin_amdgcn_sqrt(27.0 * fmax(v.disc, 0.0));
-    const double x = 27.0 * fabs(v.j3);
+    const double y = __builtin_amdgcn_sqrt(fmax(v.disc27, 0.0));
+    const double x = fabs(v.j3_27);
     const int e = __builtin_amdgcn_frexp_exp(fmax(x, y));
     const float yf = float(ldexp(y, -e));
     const float xf = float(ldexp(x, -e));
     float psi = atan2_nonneg<false>(yf, xf);
-    psi = v.j3 == v.j3 ? psi : float(v.j3); // NaN in J3 reaches the eigenvalues
+    psi = v.j3_27 == v.j3_27 ? psi : float(v.j3_27); // NaN in J3 reaches the eigenvalues
     float s, c;
     sincos_sixth<false>(psi * (1.0f / 3.0f), s, c);
-    const float r = float(__builtin_amdgcn_sqrt(fmax(v.j2, 0.0) * kThird));
+    const float r = float(__builtin_amdgcn_sqrt(fmax(v.j2_3, 0.0)));
     const float mean = float(v.i1 * kThird);
     const float a1 = -r * fma_(float(kSqrt3), s, c);
     const float a2 = r * fma_(float(kSqrt3), s, -c);
     const float a3 = 2.0f * r * c;
-    const bool neg = v.j3 < 0.0;
+    const bool neg = v.j3_27 < 0.0;
     l1 = mean + (neg ? -a3 : a1);
     l2 = mean + (neg ? -a2 : a2);
     l3 = mean + (neg ? -a1 : a3);
