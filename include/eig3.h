@@ -99,8 +99,7 @@ typedef enum eig3_layout {
 typedef enum eig3_accuracy {
     /* binary64: the paper's algorithms with fused multiply-adds.
        binary32: entries widened exactly to binary64 and the binary64 FMA
-       invariants (on gfx950 a binary64 FMA issues at the rate of a
-       non-packed binary32 one, so this is the faster binary32 variant). */
+       invariants (the paper's algorithms on the widened entries). */
     EIG3_FMA = 0,
     /* binary64: error-free products (FMA TwoProduct) and sums (TwoSum) in J2,
        J3, every r_i of dx and sum w u v: the accuracy of twice the working
@@ -111,7 +110,8 @@ typedef enum eig3_accuracy {
        binary32: K2 = 6 J2 and K3 = 27 J3 by Alg. alg:J2-stable and
        alg:J3-stable with binary32 error-free products and sums (the
        evaluation of EIG3_DOUBLE_WORD in binary32 pairs, on the deviatoric
-       data scaled by a power of two), binary64 only for the Delta
+       data, scaled by a power of two where their largest magnitude lies
+       outside [2^-10, 2^36)), binary64 only for the Delta
        accumulation (K2^3 - 2 K3^2)/54 from the widened pairs and for the
        triple-angle argument. */
     EIG3_COMPENSATED = 1,

@@ -1133,6 +1133,12 @@ struct InvW {
 // to 2^-74 times the largest stay normal, and the invariants scale back
 // exactly in binary64 (J2 by 2^2s, J3 by 2^3s, Delta by 2^6s).  Powers of two
 // commute with every rounding in between.
+// Where the largest magnitude of every matrix of the wave already lies in
+// [2^-10, 2^36) the scaling is skipped (s = 0): the products then stay below
+// 2^117, and an operation that underflows errs by at most 2^-150, a part in
+// 2^120 of the cube of the largest magnitude (2^110 of its square), on
+// which the double-word K's are accurate to about 2^-48: they keep their
+// accuracy.
 struct DevF32 {
     float d0, d1, d2, d1l; // d1 = d0 + d2 exactly as d1 + d1l
     float o[6]; // general: A01 A02 A10 A12 A20 A21; symmetric: S01 S02 S12
@@ -1148,48 +1154,62 @@ template <int KO> __device__ __forceinline__ DevF32 dev_data_f32(float a00, floa
 #pragma unroll
     for (int k = 0; k < KO; ++k)
         m = fmaxf(m, fabsf(off[k]));
-    v.sc = __builtin_amdgcn_frexp_expf(m) - 32; // frexp exponent 0 for 0, Inf, NaN
-    v.d0 = ldexpf(d[0], -v.sc);
-    v.d1 = ldexpf(d[1], -v.sc);
-    v.d2 = ldexpf(d[2], -v.sc);
-    v.d1l = ldexpf(g.d1l, -v.sc);
+    const int e = __builtin_amdgcn_frexp_expf(m); // frexp exponent 0 for 0, Inf, NaN
+    v.d0 = d[0];
+    v.d1 = d[1];
+    v.d2 = d[2];
+    v.d1l = g.d1l;
 #pragma unroll
     for (int k = 0; k < KO; ++k)
-        v.o[k] = ldexpf(off[k], -v.sc);
+        v.o[k] = off[k];
+    v.sc = 0;
+    if (!__all(e >= -9 && e <= 36)) {
+        v.sc = e - 32;
+        v.d0 = ldexpf(v.d0, -v.sc);
+        v.d1 = ldexpf(v.d1, -v.sc);
+        v.d2 = ldexpf(v.d2, -v.sc);
+        v.d1l = ldexpf(v.d1l, -v.sc);
+#pragma unroll
+        for (int k = 0; k < KO; ++k)
+            v.o[k] = ldexpf(v.o[k], -v.sc);
+    }
     return v;
 }
 
-// I1, K2 = 6 J2, K3 = 27 J3 and 54 Delta in binary64
+// I1 and K2 = 6 J2, K3 = 27 J3, 54 Delta of the deviatoric data scaled by
+// 2^-sc (binary64)
 struct KW {
     double i1, k2, k3, d54;
+    int sc;
 };
 
 __device__ __forceinline__ InvW invariants_of_kw(const KW &k)
 {
     InvW r;
     r.i1 = k.i1;
-    r.j2 = k.k2 * kSixth;
-    r.j3 = k.k3 * kTwentySeventh;
-    r.disc = k.d54 * kFiftyFourth;
+    r.j2 = ldexp(k.k2 * kSixth, 2 * k.sc);
+    r.j3 = ldexp(k.k3 * kTwentySeventh, 3 * k.sc);
+    r.disc = ldexp(k.d54 * kFiftyFourth, 6 * k.sc);
     return r;
 }
 
 // Binary32 pairs (EIG3_COMPENSATED): K2, K3 from the error-free binary32
-// evaluation of the binary64 double-word path on the prescaled deviatoric
-// data; the unrounded pairs are widened to binary64 (exactly up to 2^-53
-// relative) and 54 Delta = K2^3 - 2 K3^2 is accumulated in binary64, whose
-// rounding (~2^-53 K2^3) stays far below the pairs' own accuracy (~2^-48
-// |terms|).  Scaled back exactly (K2 by 2^2s, K3 by 2^3s, Delta by 2^6s;
-// binary32 data keep every one of them a normal binary64 number).
+// evaluation of the binary64 double-word path on the (possibly scaled)
+// deviatoric data; the unrounded pairs are widened to binary64 (exactly up
+// to 2^-53 relative) and 54 Delta = K2^3 - 2 K3^2 is accumulated in binary64,
+// whose rounding (~2^-53 K2^3) stays far below the pairs' own accuracy
+// (~2^-48 |terms|).  The scale stays attached (binary32 data keep every
+// scaled-back value a normal binary64 number).
 __device__ __forceinline__ KW kw_of_f32_pairs(double i1, const KPair<float> &k, int sc)
 {
     const double k2 = double(k.k2.hi) + double(k.k2.lo);
     const double k3 = double(k.k3.hi) + double(k.k3.lo);
     KW r;
     r.i1 = i1;
-    r.k2 = ldexp(k2, 2 * sc);
-    r.k3 = ldexp(k3, 3 * sc);
-    r.d54 = ldexp(fma_(k2 * k2, k2, -2.0 * (k3 * k3)), 6 * sc);
+    r.k2 = k2;
+    r.k3 = k3;
+    r.d54 = fma_(k2 * k2, k2, -2.0 * (k3 * k3));
+    r.sc = sc;
     return r;
 }
 
@@ -1227,6 +1247,7 @@ __device__ __forceinline__ KW kw_k64(double x00, double x11, double x22, double 
     v.k2 = k2;
     v.k3 = k3;
     v.d54 = fma_(k2 * k2, k2, -2.0 * (k3 * k3));
+    v.sc = 0;
     return v;
 }
 
@@ -1250,14 +1271,17 @@ __device__ __forceinline__ KW kw_f32_dw_symmetric(const float a[6])
 
 // The binary64 arguments of the binary32 eigenvalue tail: I1, J2 / 3,
 // 27 Delta and 27 J3 (the operands of Eq. triple-angle-arctan and of the
-// radius in Eq. eigvals-trig).
+// radius in Eq. eigvals-trig), the last three those of the deviatoric data
+// scaled by 2^-sc: the angle depends only on the ratio of sqrt(27 Delta) and
+// 27 |J3|, which scale alike (by 2^3sc), so only the radius is scaled back.
 struct TrigArgW {
     double i1, j2_3, disc27, j3_27;
+    int sc;
 };
 
 __device__ __forceinline__ TrigArgW trig_args_of_invariants(const InvW &v)
 {
-    return TrigArgW{v.i1, v.j2 * kThird, 27.0 * v.disc, 27.0 * v.j3};
+    return TrigArgW{v.i1, v.j2 * kThird, 27.0 * v.disc, 27.0 * v.j3, 0};
 }
 
 // from K2, K3 and 54 Delta: J2 / 3 = K2 / 18 in one rounding, 27 Delta =
@@ -1265,7 +1289,7 @@ __device__ __forceinline__ TrigArgW trig_args_of_invariants(const InvW &v)
 __device__ __forceinline__ TrigArgW trig_args_of_kw(const KW &k)
 {
     constexpr double kEighteenth = 1.0 / 18.0;
-    return TrigArgW{k.i1, k.k2 * kEighteenth, 0.5 * k.d54, k.k3};
+    return TrigArgW{k.i1, k.k2 * kEighteenth, 0.5 * k.d54, k.k3, k.sc};
 }
 
 // Eigenvalues in binary32 from the binary64 arguments.
@@ -1290,7 +1314,7 @@ __device__ __forceinline__ void eigvals_f32_from_args(const TrigArgW &v, float &
     psi = v.j3_27 == v.j3_27 ? psi : float(v.j3_27); // NaN in J3 reaches the eigenvalues
     float s, c;
     sincos_sixth<false>(psi * (1.0f / 3.0f), s, c);
-    const float r = float(__builtin_amdgcn_sqrt(fmax(v.j2_3, 0.0)));
+    const float r = float(ldexp(__builtin_amdgcn_sqrt(fmax(v.j2_3, 0.0)), v.sc));
     const float mean = float(v.i1 * kThird);
     const float a1 = -r * fma_(float(kSqrt3), s, c);
     const float a2 = r * fma_(float(kSqrt3), s, -c);

@@ -157,6 +157,30 @@ def test_f32_power_of_two_scales(eig3, acc, k):
         assert np.all(np.diff(lam, axis=1) >= 0)
 
 
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_f32_compensated_scaling_window(eig3, c4, layout):
+    """The binary32-compensated evaluation scales the deviatoric data by a
+    power of two unless every matrix of the wave has its largest magnitude in
+    [2^-10, 2^36).  The stress tensors lie inside that window; the same
+    tensors are evaluated once alone (every wave skips the scaling) and once
+    with every 64th tensor replaced by a copy times 2^100 (every wave that
+    holds one scales all its matrices): both runs are within the bounds of
+    the exact eigenvalues, and the replaced tensors within theirs."""
+    s, t = c4
+    lam_skip = download_lam(eig3.eig3_eigvals(upload(s, layout, "symmetric"), "symmetric", "compensated", "soa"))
+    mixed = s.copy()
+    far = np.arange(0, s.shape[0], 64)
+    mixed[far] = (s[far].astype(np.float64) * 2.0 ** 100).astype(np.float32)
+    lam_mix = download_lam(eig3.eig3_eigvals(upload(mixed, layout, "symmetric"), "symmetric", "compensated", "soa"))
+    keep = np.setdiff1d(np.arange(s.shape[0]), far)
+    b = t.bound_lam(EPS32)
+    err_skip, err_mix = lam_errors(t, lam_skip), lam_errors(t, lam_mix)
+    check(err_skip, b, what=f"f32 compensated, no scaling ({layout})")
+    check(err_mix[keep], b[keep], what=f"f32 compensated, scaled waves ({layout})")
+    tf = Truth(w.symmetric_to_general(mixed[far].astype(np.float64)), np.ones(far.size))
+    check(lam_errors(tf, lam_mix[far]), tf.bound_lam(EPS32), what=f"f32 compensated, 2^100 tensors ({layout})")
+
+
 @pytest.mark.parametrize("acc", ACCS)
 def test_f32_special_matrices(eig3, acc):
     """Zero, scaled identity (J2 = 0), exact double roots (Delta = 0), J3 = 0
