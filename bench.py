@@ -171,15 +171,25 @@ def within_8x(rep, workload, mode):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name, from /proc/cpuinfo."""
+    """The host CPU's model name with its family, model and stepping numbers
+    and its widest vector extension, from /proc/cpuinfo (a virtualised host
+    may report only a generic name)."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # the first processor's block is enough
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    flags = fields.get("flags", "").split()
+    vec = next((v for v in ("avx512f", "avx2", "sse4_2") if v in flags), "")
+    ident = ", ".join(f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields)
+    extra = "; ".join(x for x in (ident, vec) if x)
+    name = fields.get("model name", "unknown")
+    return f"{name} ({extra})" if extra else name
 
 
 def cpu_clock() -> dict:
@@ -540,7 +550,8 @@ def main():
                          f"over {cores} threads, gcc -O2 -ffp-contract=off); value = best of the 3",
                "single_core": {"value": rates1[-1], "median_of_3": rates1[1], "unit": "matrices/s", "cores": 1,
                                "sample": f"3 x {passes1} passes over {sample_n >> 4} matrices"},
-               "cpu_model": cpu_model(), "cpu_clock": cpu_clock()}
+               "cpu_model": cpu_model(), "cpu_clock": cpu_clock(),
+               "host_logical_cpus": os.cpu_count(), "cpus_available": len(os.sched_getaffinity(0))}
         log(f"cpu baseline {rates[-1] / 1e6:.1f} M mat/s on {cores} threads (median {rates[1] / 1e6:.1f}), "
             f"{rates1[-1] / 1e6:.2f} M mat/s on 1")
 
