@@ -54,7 +54,7 @@
  *    EIG3_DOUBLE_WORD and EIG3_COMPENSATED stay within a small multiple of
  *    these bounds also for ill-conditioned eigenbases (measured on the
  *    synthetic workloads up to kappa_2 = 100, and on the paper's own paths
- *    with kappa_2 ~ 9e3: worst 3.7x for every invariant and eigenvalue),
+ *    with kappa_2 ~ 9e3: worst 3.8x for every invariant and eigenvalue),
  *    where the plain algorithms (EIG3_FMA, and the paper's algorithms in
  *    plain binary64) exceed them by up to three orders of magnitude.
  */
