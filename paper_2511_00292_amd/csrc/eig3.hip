@@ -423,15 +423,27 @@ template <int S, int Acc> __device__ __forceinline__ TrigArgW f32_args_of(const 
 // the scaling is skipped: nothing then over- or underflows that the scaled
 // evaluation would keep, and the results are bitwise those of the scaled
 // evaluation (every operation commutes with an exact power of two).
+// (The window test compares the entries' high words with the sign cleared:
+// they order the entries by magnitude up to the low word, so their maximum
+// carries the binade of the largest entry; a zero, infinite or NaN entry
+// fails it and its wave takes the exact exponent below, which scales such
+// matrices by 2^0 as before.)
 template <int S> __device__ __forceinline__ int prescale(Mat<double, S> &m)
 {
+    uint32_t h = 0;
+#pragma unroll
+    for (int k = 0; k < Mat<double, S>::K; ++k) {
+        const uint32_t hk = uint32_t(__builtin_bit_cast(uint64_t, m.a[k]) >> 32) & 0x7fffffffu;
+        h = hk > h ? hk : h;
+    }
+    // biased exponent of the largest entry in [959, 1086]: frexp exponent in [-63, 64]
+    if (__all(h - (959u << 20) < (128u << 20)))
+        return 0;
     double mx = 0.0;
 #pragma unroll
     for (int k = 0; k < Mat<double, S>::K; ++k)
         mx = fmax(mx, fabs(m.a[k]));
     const int e = __builtin_amdgcn_frexp_exp(mx); // 0 for 0, Inf and NaN: no scaling
-    if (__all(e >= -63 && e <= 64))
-        return 0;
 #pragma unroll
     for (int k = 0; k < Mat<double, S>::K; ++k)
         m.a[k] = ldexp(m.a[k], -e);
