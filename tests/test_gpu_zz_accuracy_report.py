@@ -46,6 +46,40 @@ def _outputs(x_inv, x_lam, o1_inv, o1_lam, t, eps):
     return res
 
 
+def _by_decade(variant, kappa, decade, t, per):
+    """Worst eigenvalue and Delta error (units of the bound, against the
+    exact result) per decade of the sweep's perturbation d, for each
+    evaluation and for O1."""
+    bl, bd = t.bound_lam(EPS64), t.bound_inv(EPS64)[:, 3]
+    out = []
+    for dec in np.unique(decade):
+        m = decade == dec
+        rec = {"variant": variant, "kappa": kappa, "decade": int(dec), "n": int(m.sum())}
+        for src, (inv, lam) in per.items():
+            el = np.abs(lam[m] - t.lam.real[m]) / np.maximum(bl[m], 1e-300)
+            ed = np.abs(inv[m, 3] - t.inv[m, 3]) / np.maximum(bd[m], 1e-300)
+            rec[src] = {"eigvals": float(el.max()), "Delta": float(ed.max())}
+        out.append(rec)
+    return out
+
+
+def _decade_markdown(rep):
+    """Per (kappa, decade of d): the worst over the sweep's three variants."""
+    srcs = ("double_word", "compensated", "fma", "O1")
+    lines = ["", "Perturbation sweep by decade of d (worst over its three variants; GPU and O1 against O2, "
+             "units of the bound, max):", "",
+             "| kappa | d in | n | " + " | ".join(f"eigvals {s}" for s in srcs) + " | "
+             + " | ".join(f"Delta {s}" for s in srcs) + " |",
+             "|---|---|---|" + "---|" * (2 * len(srcs))]
+    keys = sorted({(r["kappa"], r["decade"]) for r in rep["sweep_decades"]})
+    for kappa, dec in keys:
+        rs = [r for r in rep["sweep_decades"] if r["kappa"] == kappa and r["decade"] == dec]
+        cells = [f"{max(r[s]['eigvals'] for r in rs):.3g}" for s in srcs] + \
+                [f"{max(r[s]['Delta'] for r in rs):.3g}" for s in srcs]
+        lines.append(f"| {kappa:g} | [1e{dec}, 1e{dec + 1}) | {sum(r['n'] for r in rs)} | " + " | ".join(cells) + " |")
+    return lines
+
+
 def _markdown(rep):
     lines = ["# Forward errors per workload, evaluation and output", "",
              "Command: `EIG3_ACCURACY_REPORT=<dir> python -m pytest tests/test_gpu_zz_accuracy_report.py -m gpu`", "",
@@ -67,33 +101,38 @@ def _markdown(rep):
               "| evaluation | max rel. error | paper route (plain binary64 eigenprojectors) |", "|---|---|---|"]
     for mode, v in rep["adjoint"].items():
         lines.append(f"| {mode} | {v['gpu']:.2e} | {v['paper_route']:.2e} |")
+    lines += _decade_markdown(rep)
     return "\n".join(lines) + "\n"
 
 
 def test_accuracy_report(plain_oracle):
     import paper_2511_00292_amd as eig3
     rep = {"units": "forward error / stability bound (C = 1, Frobenius, second-order term included)",
-           "rows": [], "adjoint": {}}
+           "rows": [], "adjoint": {}, "sweep_decades": []}
 
     def general(name, a, kappa, eps=EPS64, a_dev=None, seed_note=""):
         t = Truth(a, kappa)
         o1_inv = np.stack(plain_oracle.invariants(a), axis=1)
         o1_lam = plain_oracle.eigvals(a)
         dev = upload(a, "soa") if a_dev is None else a_dev
+        per = {"O1": (o1_inv, o1_lam)}
         for acc in MODES:
             lam = download_lam(eig3.eig3_eigvals(dev, "general", acc, "soa"))
             inv = download_inv(eig3.eig3_invariants(dev, "general", acc))
             rep["rows"].append({"workload": name, "mode": acc, "n": int(a.shape[0]),
                                 "outputs": _outputs(inv, lam, o1_inv, o1_lam, t, eps)})
-        return t
+            per[acc] = (inv, lam)
+        return t, per
 
     general("Haar-similar batch, general f64", w.haar_general(1500, seed=12)["a"], 1.0)
     cb = w.perturbation_sweep(9 * 4096, seed=16)
     names = {0: "diag(1, 1+d, 1+2d)", 1: "diag(1, 1, 1+d)", 2: "I + d S"}
+    decades = np.floor(np.log10(cb["delta"])).astype(int)
     for v in range(3):
         for kappa in (1.0, 10.0, 100.0):
             sel = (cb["variant"] == v) & (cb["kappa"] == kappa)
-            general(f"perturbation sweep {names[v]} kappa={kappa:g}, general f64", cb["a"][sel], kappa)
+            t, per = general(f"perturbation sweep {names[v]} kappa={kappa:g}, general f64", cb["a"][sel], kappa)
+            rep["sweep_decades"] += _by_decade(names[v], kappa, decades[sel], t, per)
     c5 = w.differentiation_batch(1500, seed=15)
     general("differentiation batch, general f64", c5["a"], c5["kappa"])
     # the same batch stored in binary32 (eigenvalues; bounds with eps = 2^-24
