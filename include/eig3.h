@@ -16,9 +16,12 @@
  *   phi = atan2(sqrt(27 Delta), 27 J3) in [0, pi].
  *
  * Conventions shared by every call:
- *  - All data pointers are DEVICE pointers owned by the caller.  The library
- *    never allocates, frees or synchronizes; each call only enqueues kernels
- *    on `stream` (a hipStream_t; NULL = the default stream) and returns.
+ *  - All data pointers are DEVICE pointers owned by the caller, on the
+ *    calling thread's current HIP device, which is where the kernels run
+ *    (`stream` must belong to that device).  The library never allocates,
+ *    frees or synchronizes and keeps no state between calls, so it may be
+ *    called from several threads at once; each call only enqueues kernels on
+ *    `stream` (a hipStream_t; NULL = the default stream) and returns.
  *  - Inputs are read-only.  Outputs must not alias inputs or each other.
  *  - n == 0 is a no-op returning EIG3_OK.  Invalid arguments (NULL pointers,
  *    pointers not aligned to the element size, n < 0 or n > 2^56, unknown
