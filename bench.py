@@ -85,21 +85,29 @@ def profile_set():
     torch.cuda.synchronize()
     del src, dst
     c5 = w.differentiation_batch(N_MAIN)
-    a = [torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])).to(dev) for k in range(9)]
-    g = [torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])).to(dev) for k in range(3)]
+    arrs = eig3.empty_soa(N_MAIN, 24, torch.float64, dev)
+    a, g, lam, grad = arrs[:9], arrs[9:12], arrs[12:15], arrs[15:]
+    for k in range(9):
+        a[k].copy_(torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])))
+    for k in range(3):
+        g[k].copy_(torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])))
     for acc in ("double_word", "fma", "compensated"):
-        eig3.eig3_eigvals(a, "general", acc, "soa")
-        eig3.eig3_eigvals_backward(a, g, "general", acc)
+        eig3.eig3_eigvals(a, "general", acc, "soa", out=lam)
+        eig3.eig3_eigvals_backward(a, g, "general", acc, out=grad)
     torch.cuda.synchronize()
-    del a, g
+    del a, g, lam, grad, arrs
     s = w.stress_tensors(N_SYM)["s"]
-    s64 = [torch.from_numpy(np.ascontiguousarray(s[:, k])).to(dev) for k in range(6)]
+    arrs = eig3.empty_soa(N_SYM, 9, torch.float64, dev)
+    for k in range(6):
+        arrs[k].copy_(torch.from_numpy(np.ascontiguousarray(s[:, k])))
     for acc in ("double_word", "fma"):
-        eig3.eig3_eigvals(s64, "symmetric", acc, "soa")
-    s32 = [t.float() for t in s64]
-    del s64
+        eig3.eig3_eigvals(arrs[:6], "symmetric", acc, "soa", out=arrs[6:])
+    arrs32 = eig3.empty_soa(N_SYM, 9, torch.float32, dev)
+    for k in range(6):
+        arrs32[k].copy_(arrs[k])
+    del arrs
     for acc in ("double_word", "fma", "compensated"):
-        eig3.eig3_eigvals(s32, "symmetric", acc, "soa")
+        eig3.eig3_eigvals(arrs32[:6], "symmetric", acc, "soa", out=arrs32[6:])
     torch.cuda.synchronize()
     log("profile set done")
 
@@ -339,10 +347,14 @@ def main():
     t0 = time.perf_counter()
     c5 = w.differentiation_batch(N_MAIN)
     log(f"differentiation batch generated n={N_MAIN} in {time.perf_counter() - t0:.1f}s")
-    a = [torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])).to(dev) for k in range(9)]
-    g = [torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])).to(dev) for k in range(3)]
-    lam = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(3)]
-    grad = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
+    # A, g, the eigenvalues and the gradient: 24 arrays in one buffer at the
+    # library's recommended stride (eig3_soa_stride)
+    arrs = eig3.empty_soa(N_MAIN, 24, torch.float64, dev)
+    a, g, lam, grad = arrs[:9], arrs[9:12], arrs[12:15], arrs[15:24]
+    for k in range(9):
+        a[k].copy_(torch.from_numpy(np.ascontiguousarray(c5["a"][:, k])))
+    for k in range(3):
+        g[k].copy_(torch.from_numpy(np.ascontiguousarray(c5["g"][:, k])))
     del c5
     acc = args.accuracy
     # the copy ceiling first: it also brings the GPU clock back up after the
@@ -424,16 +436,26 @@ def main():
                     lambda acc_v=acc_v: (eig3.eig3_eigvals(a, "general", acc_v, "soa", out=lam),
                                          eig3.eig3_eigvals_backward(a, g, "general", acc_v, out=grad)), "f64",
                     acc_v, W5)
+        # the same arrays as 24 separate allocations
+        a_s, g_s = [t.clone() for t in a], [t.clone() for t in g]
+        lam_s = [torch.empty_like(t) for t in lam]
+        grad_s = [torch.empty_like(t) for t in grad]
+        variant("differentiation batch step f64 (double_word forward + adjoint), separate allocations",
+                "step_general_f64", N_MAIN,
+                lambda: (eig3.eig3_eigvals(a_s, "general", "double_word", "soa", out=lam_s),
+                         eig3.eig3_eigvals_backward(a_s, g_s, "general", "double_word", out=grad_s)), "f64",
+                "double_word", W5)
+        del a_s, g_s, lam_s, grad_s
         # eigenprojectors E_1..E_3 (27 outputs per matrix, write-heavy)
-        eproj = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(27)]
+        eproj = eig3.empty_soa(N_MAIN, 27, torch.float64, dev)
         variant("differentiation batch eigenprojectors general f64 double_word", "eigenprojectors_general_f64",
                 N_MAIN, lambda: eig3.eig3_eigenprojectors(a, "general", "double_word", "soa", out=eproj), "f64")
         del eproj
         # a function of each matrix through the eigenprojectors (9 outputs)
-        fexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
+        fexp = eig3.empty_soa(N_MAIN, 9, torch.float64, dev)
         variant("differentiation batch matrix exponential general f64 double_word", "matrix_function_general_f64",
                 N_MAIN, lambda: eig3.eig3_matrix_function(a, "exp", "general", "double_word", out=fexp), "f64")
-        gexp = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(9)]
+        gexp = eig3.empty_soa(N_MAIN, 9, torch.float64, dev)
         variant("differentiation batch matrix exponential adjoint general f64 double_word",
                 "matrix_function_backward_general_f64", N_MAIN,
                 lambda: eig3.eig3_matrix_function_backward(a, fexp, "exp", "general", "double_word", out=gexp), "f64")
@@ -453,10 +475,12 @@ def main():
         del a_aos, lam_aos, g_aos, grad_aos
         # the same workload stored in binary32: forward in each evaluation,
         # the adjoint (binary64 arithmetic, rounded once), and the whole step
-        a32 = [t.float() for t in a]
-        g32 = [t.float() for t in g]
-        lam32 = [torch.empty(N_MAIN, dtype=torch.float32, device=dev) for _ in range(3)]
-        grad32 = [torch.empty(N_MAIN, dtype=torch.float32, device=dev) for _ in range(9)]
+        arrs32 = eig3.empty_soa(N_MAIN, 24, torch.float32, dev)
+        a32, g32, lam32, grad32 = arrs32[:9], arrs32[9:12], arrs32[12:15], arrs32[15:24]
+        for k in range(9):
+            a32[k].copy_(a[k])
+        for k in range(3):
+            g32[k].copy_(g[k])
         for acc_v in ("double_word", "fma", "compensated"):
             variant(f"differentiation batch fwd general f32 {acc_v}", "fwd_general_f32", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a32, "general", acc_v, "soa", out=lam32), "f32", acc_v,
@@ -470,49 +494,65 @@ def main():
                 eig3.eig3_eigvals_backward(a32, g32, "general", acc_v, out=grad32)
             variant(f"differentiation batch step f32 ({acc_v} forward + adjoint)", "step_general_f32", N_MAIN,
                     step32, "f32", acc_v)
-        del a, g, lam, grad, a32, g32, lam32, grad32
+        del a, g, lam, grad, arrs, a32, g32, lam32, grad32, arrs32
         torch.cuda.empty_cache()
         # the perturbation sweep
         t0 = time.perf_counter()
         c2 = w.perturbation_sweep(N_MAIN)
         log(f"perturbation sweep generated in {time.perf_counter() - t0:.1f}s")
-        a2 = [torch.from_numpy(np.ascontiguousarray(c2["a"][:, k])).to(dev) for k in range(9)]
+        arrs2 = eig3.empty_soa(N_MAIN, 12, torch.float64, dev)
+        a2, l2 = arrs2[:9], arrs2[9:]
+        for k in range(9):
+            a2[k].copy_(torch.from_numpy(np.ascontiguousarray(c2["a"][:, k])))
         del c2
-        l2 = [torch.empty(N_MAIN, dtype=torch.float64, device=dev) for _ in range(3)]
         for acc_v in ("double_word", "fma", "compensated"):
             variant(f"perturbation sweep fwd general f64 {acc_v}", "fwd_general_f64", N_MAIN,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(a2, "general", acc_v, "soa", out=l2), "f64", acc_v,
                     "perturbation sweep ")
-        del a2, l2
+        del a2, l2, arrs2
         torch.cuda.empty_cache()
         # symmetric stress tensors in binary64 and binary32
         t0 = time.perf_counter()
         c3 = w.stress_tensors(N_SYM)
         log(f"stress tensors generated in {time.perf_counter() - t0:.1f}s")
-        s64 = [torch.from_numpy(np.ascontiguousarray(c3["s"][:, k])).to(dev) for k in range(6)]
-        l3 = [torch.empty(N_SYM, dtype=torch.float64, device=dev) for _ in range(3)]
+        arrs3 = eig3.empty_soa(N_SYM, 9, torch.float64, dev)
+        s64, l3 = arrs3[:6], arrs3[6:]
+        for k in range(6):
+            s64[k].copy_(torch.from_numpy(np.ascontiguousarray(c3["s"][:, k])))
         for acc_v in ("double_word", "fma", "compensated"):
             variant(f"stress tensors fwd symmetric f64 {acc_v}", "fwd_symmetric_f64", N_SYM,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(s64, "symmetric", acc_v, "soa", out=l3), "f64", acc_v,
                     "stress tensors, symmetric f64")
-        del l3
+        # the same arrays as 9 separate allocations
+        s64_s = [t.clone() for t in s64]
+        l3_s = [torch.empty_like(t) for t in l3]
+        variant("stress tensors fwd symmetric f64 fma, separate allocations", "fwd_symmetric_f64", N_SYM,
+                lambda: eig3.eig3_eigvals(s64_s, "symmetric", "fma", "soa", out=l3_s), "f64", "fma",
+                "stress tensors, symmetric f64")
+        del s64_s, l3_s, l3
         # the paper's application: Mohr-Coulomb f and df/dsigma (S_yc = 100, m = 10)
-        f_mc = torch.empty(N_SYM, dtype=torch.float64, device=dev)
-        g_mc = [torch.empty(N_SYM, dtype=torch.float64, device=dev) for _ in range(6)]
+        f_mc, *g_mc = eig3.empty_soa(N_SYM, 7, torch.float64, dev)
         for acc_v in ("fma", "double_word"):
             variant(f"stress tensors mohr-coulomb f + df/dsigma symmetric f64 {acc_v}", "mohr_coulomb_symmetric_f64",
                     N_SYM, lambda acc_v=acc_v: eig3.eig3_mohr_coulomb(s64, 100.0, 10.0, "symmetric", acc_v, True,
                                                                       out=(f_mc, g_mc)), "f64")
         del f_mc, g_mc
-        s32 = [t.float() for t in s64]
-        del s64
+        arrs4 = eig3.empty_soa(N_SYM, 9, torch.float32, dev)
+        s32, l4 = arrs4[:6], arrs4[6:]
+        for k in range(6):
+            s32[k].copy_(s64[k])
+        del s64, arrs3
         torch.cuda.empty_cache()
-        l4 = [torch.empty(N_SYM, dtype=torch.float32, device=dev) for _ in range(3)]
         for acc_v in ("double_word", "compensated", "fma"):
             variant(f"binary32 stress tensors fwd symmetric f32 {acc_v}", "fwd_symmetric_f32", N_SYM,
                     lambda acc_v=acc_v: eig3.eig3_eigvals(s32, "symmetric", acc_v, "soa", out=l4), "f32", acc_v,
                     "binary32 stress tensors, symmetric f32")
-        del s32, l4, c3
+        s32_s = [t.clone() for t in s32]
+        l4_s = [torch.empty_like(t) for t in l4]
+        variant("binary32 stress tensors fwd symmetric f32 double_word, separate allocations", "fwd_symmetric_f32",
+                N_SYM, lambda: eig3.eig3_eigvals(s32_s, "symmetric", "double_word", "soa", out=l4_s), "f32",
+                "double_word", "binary32 stress tensors, symmetric f32")
+        del s32, l4, arrs4, s32_s, l4_s, c3
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ CPU leg
@@ -572,6 +612,7 @@ def main():
                                "A = V diag(l) V^-1 (sorted l ~ U[-1,1], gap >= 1e-3, cond(V) = 10^U(0,2)); "
                                "step = eig3_eigvals + eig3_eigvals_backward, structure-of-arrays",
                    "n": N_MAIN, "accuracy": acc, "layout": "soa",
+                   "placement": "A, g, eigenvalues and gradient: 24 arrays in one buffer at eig3_soa_stride",
                    "within_8x_bound": within_8x(rep, W5, acc),
                    "step_GB_per_s": round((BYTES["fwd_general_f64"] + BYTES["bwd_general_f64"]) * N_MAIN
                                           / (ms * 1e-3) / 1e9, 1),

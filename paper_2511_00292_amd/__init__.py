@@ -28,7 +28,7 @@ __all__ = [
     "eig3_matrix_function", "eig3_matrix_function_backward", "eigvals", "eigvals_symmetric", "matrix_function",
     "matrix_function_symmetric", "Eig3Eigvals", "Eig3EigvalsSymmetric", "Eig3MatrixFunction",
     "Eig3MatrixFunctionSymmetric",
-    "ENTRIES", "Eig3Error", "version",
+    "ENTRIES", "Eig3Error", "version", "soa_stride", "empty_soa",
 ]
 
 ENTRIES = {
@@ -49,6 +49,26 @@ def version() -> str:
     return _capi.version()
 
 
+def soa_stride(n: int, dtype=torch.float64) -> int:
+    """eig3_soa_stride: the recommended distance, in elements, between
+    consecutive arrays of a structure-of-arrays batch of n matrices held in
+    one allocation (see include/eig3.h)."""
+    if dtype not in _DTYPE:
+        raise TypeError("dtype must be torch.float64 or torch.float32")
+    return _capi.soa_stride(n, _DTYPE[dtype])
+
+
+def empty_soa(n: int, count: int, dtype=torch.float64, device=None) -> list:
+    """count uninitialised arrays of n values in one device allocation,
+    array k at element k * soa_stride(n, dtype): the placement the library
+    recommends for structure-of-arrays batches and their outputs.  The arrays
+    are views of one buffer, which stays allocated while any of them is
+    alive."""
+    stride = soa_stride(n, dtype)
+    buf = torch.empty(count * stride, dtype=dtype, device=device)
+    return [buf[k * stride: k * stride + n] for k in range(count)]
+
+
 def _check_device_tensor(t: torch.Tensor, what: str) -> None:
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{what} must be a torch.Tensor")
@@ -67,7 +87,7 @@ def _check_out(t: torch.Tensor, numel: int, dtype, device, what: str) -> None:
 
 
 def _out_list(out, count: int, n: int, dtype, device, what: str) -> list:
-    res = list(out) if out is not None else [torch.empty(n, dtype=dtype, device=device) for _ in range(count)]
+    res = list(out) if out is not None else empty_soa(n, count, dtype, device)
     if len(res) != count:
         raise ValueError(f"{what} needs {count} tensors")
     for j, t in enumerate(res):

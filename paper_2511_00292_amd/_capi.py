@@ -73,6 +73,8 @@ def lib():
         l.eig3_status_string.restype = ctypes.c_char_p
         l.eig3_version.argtypes = []
         l.eig3_version.restype = ctypes.c_char_p
+        l.eig3_soa_stride.argtypes = [ctypes.c_int64, ctypes.c_int32]
+        l.eig3_soa_stride.restype = ctypes.c_int64
         _lib = l
     return _lib
 
@@ -83,6 +85,13 @@ def status_string(status: int) -> str:
 
 def version() -> str:
     return lib().eig3_version().decode()
+
+
+def soa_stride(n: int, dtype: int) -> int:
+    s = lib().eig3_soa_stride(int(n), int(dtype))
+    if s < 0:
+        raise Eig3Error(EIG3_EINVAL, "eig3_soa_stride")
+    return s
 
 
 def declared_functions() -> list[str]:

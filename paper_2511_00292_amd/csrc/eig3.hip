@@ -1083,6 +1083,15 @@ int eig3_matrix_function_backward(const eig3_matrices *A, int32_t fn, const void
 
 const char *eig3_version(void) { return "0.1.0"; }
 
+int64_t eig3_soa_stride(int64_t n, int32_t dtype)
+{
+    if (n < 0 || n > kMaxMatrices || !valid_enum(dtype, 1))
+        return -1;
+    constexpr int64_t kRound = int64_t(64) << 10, kStagger = int64_t(8) << 10;
+    const int64_t size = dtype == EIG3_F64 ? 8 : 4;
+    return ((n * size + kRound - 1) / kRound * kRound + kStagger) / size;
+}
+
 int eig3_invariants(const eig3_matrices *A, void *i1, void *j2, void *j3, void *disc, hipStream_t stream)
 {
     int st = check_matrices(A);

@@ -158,3 +158,33 @@ def test_matrix_function_backward_arguments(lib):
     assert lib.eig3_matrix_function_backward(ctypes.byref(m), 0, g, alias, None) == capi.EIG3_EINVAL  # grad aliases g
     gnull = (ctypes.c_void_p * 9)(*([0x30000000] * 8 + [0]))
     assert lib.eig3_matrix_function_backward(ctypes.byref(m), 0, gnull, outs, None) == capi.EIG3_EINVAL
+
+
+def test_soa_stride(lib):
+    """eig3_soa_stride: n elements rounded up to a multiple of 64 KiB, plus
+    8 KiB, counted in elements of the dtype; -1 for invalid arguments."""
+    for n, dtype, size in ((0, 0, 8), (1, 0, 8), (1 << 24, 0, 8), (1 << 27, 1, 4), (10 ** 7, 0, 8), (12345, 1, 4),
+                           (1 << 56, 0, 8)):
+        stride = lib.eig3_soa_stride(n, dtype)
+        pad = stride * size - 8192
+        assert pad % 65536 == 0 and 0 <= pad - n * size < 65536, (n, dtype, stride)
+    assert lib.eig3_soa_stride(-1, 0) == -1
+    assert lib.eig3_soa_stride(16, 2) == -1
+    assert lib.eig3_soa_stride((1 << 56) + 1, 0) == -1
+
+
+def test_empty_soa_views():
+    """The Python helper: count disjoint contiguous arrays of n values in one
+    buffer, array k at element k * stride."""
+    import torch
+
+    import paper_2511_00292_amd as eig3
+    for n, dtype in ((1000, torch.float64), (1 << 16, torch.float32), (0, torch.float64)):
+        arrays = eig3.empty_soa(n, 5, dtype, device="cpu")
+        stride = eig3.soa_stride(n, dtype)
+        assert [t.numel() for t in arrays] == [n] * 5 and all(t.is_contiguous() and t.dtype == dtype for t in arrays)
+        if n:
+            base = arrays[0].data_ptr()
+            assert [t.data_ptr() - base for t in arrays] == [k * stride * arrays[0].element_size() for k in range(5)]
+    with pytest.raises(capi.Eig3Error):
+        eig3.soa_stride(-5)

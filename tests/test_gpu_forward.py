@@ -181,3 +181,26 @@ def test_aos_unaligned_offset(eig3):
     view = big[3:3 + 700 * 9]
     lam = download_lam(eig3.eig3_eigvals(view, "general", "double_word", "aos"))
     check(lam_errors(t, lam), t.bound_lam(), what="aos offset 3")
+
+
+def test_staggered_one_buffer_placement(eig3):
+    """Arrays placed in one buffer at eig3.soa_stride (the library's default
+    for its own outputs) give bitwise the results of separate allocations,
+    forward and adjoint, with ragged n."""
+    import torch
+    n = 70_001
+    c = w.differentiation_batch(n)
+    a, g = np.ascontiguousarray(c["a"]), np.ascontiguousarray(c["g"])
+    sep_a, sep_g = upload(a, "soa"), upload(g, "soa")
+    one = eig3.empty_soa(n, 12, torch.float64, device=sep_a[0].device)
+    for k in range(9):
+        one[k].copy_(sep_a[k])
+    for k in range(3):
+        one[9 + k].copy_(sep_g[k])
+    for acc in ("double_word", "fma"):
+        lam_sep = download_lam(eig3.eig3_eigvals(sep_a, "general", acc, "soa"))
+        lam_one = download_lam(eig3.eig3_eigvals(one[:9], "general", acc, "soa"))
+        assert np.array_equal(lam_sep, lam_one)
+        g_sep = download_inv(eig3.eig3_eigvals_backward(sep_a, sep_g, "general", acc))
+        g_one = download_inv(eig3.eig3_eigvals_backward(one[:9], one[9:], "general", acc))
+        assert np.array_equal(g_sep, g_one)
