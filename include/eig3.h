@@ -295,16 +295,18 @@ int eig3_matrix_function_backward(const eig3_matrices *A, int32_t fn, const void
 /* Placement of a structure-of-arrays batch: the recommended distance, in
  * elements of the given dtype, between consecutive arrays of a batch of n
  * matrices stored in one allocation (array k at element k * stride): n
- * elements rounded up to a multiple of 64 KiB, plus 8 KiB.  The same index
+ * elements rounded up to a multiple of 64 KiB, plus 42 KiB.  The same index
  * of every array is read and written at the same time; arrays that start
  * at the same offset within large power-of-two blocks (separate large
  * allocations, for instance) can then meet on the same HBM channels, and on
- * MI355X that cost the symmetric binary64 forward kernel 8 points of HBM
- * bandwidth on 2^27 matrices (69% against 77% of 8 TB/s, 9 arrays of
- * 1 GiB); the 8 KiB stagger between consecutive arrays removes it.  Every
- * array start keeps the alignment of the buffer up to 8 KiB.  A pure
- * function: no device access.  Returns -1 for n < 0, n > 2^56 or an unknown
- * dtype. */
+ * MI355X that cost the symmetric binary64 forward kernel up to 10 points of
+ * HBM bandwidth (68% against 78% of 8 TB/s on 2^26 matrices).  A stagger
+ * that is a single power of two can itself cancel against one address bit
+ * of the array size (8 KiB measured 62% on 2^25 general binary64
+ * matrices); 42 KiB = 32 + 8 + 2 KiB measured 71-80% on every size from
+ * 2^22 to 2^28 matrices.  Every array start keeps the alignment of the
+ * buffer up to 2 KiB.  A pure function: no device access.  Returns -1 for
+ * n < 0, n > 2^56 or an unknown dtype. */
 int64_t eig3_soa_stride(int64_t n, int32_t dtype);
 
 /* Static, human-readable name of a status code. */

@@ -1087,7 +1087,9 @@ int64_t eig3_soa_stride(int64_t n, int32_t dtype)
 {
     if (n < 0 || n > kMaxMatrices || !valid_enum(dtype, 1))
         return -1;
-    constexpr int64_t kRound = int64_t(64) << 10, kStagger = int64_t(8) << 10;
+    // 42 KiB = 32 + 8 + 2 KiB: three address bits, so that no single high
+    // address bit of an array size can cancel the stagger in the interleave
+    constexpr int64_t kRound = int64_t(64) << 10, kStagger = int64_t(42) << 10;
     const int64_t size = dtype == EIG3_F64 ? 8 : 4;
     return ((n * size + kRound - 1) / kRound * kRound + kStagger) / size;
 }

@@ -162,11 +162,11 @@ def test_matrix_function_backward_arguments(lib):
 
 def test_soa_stride(lib):
     """eig3_soa_stride: n elements rounded up to a multiple of 64 KiB, plus
-    8 KiB, counted in elements of the dtype; -1 for invalid arguments."""
+    42 KiB, counted in elements of the dtype; -1 for invalid arguments."""
     for n, dtype, size in ((0, 0, 8), (1, 0, 8), (1 << 24, 0, 8), (1 << 27, 1, 4), (10 ** 7, 0, 8), (12345, 1, 4),
                            (1 << 56, 0, 8)):
         stride = lib.eig3_soa_stride(n, dtype)
-        pad = stride * size - 8192
+        pad = stride * size - 43008
         assert pad % 65536 == 0 and 0 <= pad - n * size < 65536, (n, dtype, stride)
     assert lib.eig3_soa_stride(-1, 0) == -1
     assert lib.eig3_soa_stride(16, 2) == -1
