@@ -5,7 +5,8 @@
  *   c_caller <n> <a.bin> <g.bin> <lam.bin> <inv.bin> <grad.bin>
  *
  * a.bin: n general binary64 matrices, row-major (n, 9); g.bin: (n, 3).
- * The matrices go to the device as 9 structure-of-arrays columns, the
+ * The matrices go to the device as 9 structure-of-arrays columns (with the
+ * gradient's 9, in one allocation at eig3_soa_stride), the
  * results come back as lam (n, 3), inv (n, 4: I1 J2 J3 Delta) and grad
  * (n, 9).  Exit status 0 on success; any HIP or eig3 error prints a message
  * and exits non-zero.
@@ -75,9 +76,18 @@ int main(int argc, char **argv)
     hipStream_t stream;
     HIP_OK(hipStreamCreate(&stream));
     double *da[9], *dg[3], *dl[3], *di[4], *dgr[9];
+    /* A and the gradient: 18 arrays in one allocation at the recommended
+       stride; g, the eigenvalues and the invariants: separate allocations */
+    const int64_t stride = eig3_soa_stride(n, EIG3_F64);
+    if (stride < n) {
+        fprintf(stderr, "eig3_soa_stride returned %lld\n", (long long)stride);
+        return 3;
+    }
+    double *dbuf;
+    HIP_OK(hipMalloc((void **)&dbuf, 18 * (size_t)stride * sizeof(double)));
     for (int k = 0; k < 9; ++k) {
-        HIP_OK(hipMalloc((void **)&da[k], bytes));
-        HIP_OK(hipMalloc((void **)&dgr[k], bytes));
+        da[k] = dbuf + (size_t)k * (size_t)stride;
+        dgr[k] = dbuf + (size_t)(9 + k) * (size_t)stride;
         for (size_t m = 0; m < nn; ++m)
             col[m] = a[9 * m + k];
         HIP_OK(hipMemcpy(da[k], col, bytes, hipMemcpyHostToDevice));
@@ -135,10 +145,7 @@ int main(int argc, char **argv)
     }
     write_file(argv[6], out, nn * 9);
 
-    for (int k = 0; k < 9; ++k) {
-        HIP_OK(hipFree(da[k]));
-        HIP_OK(hipFree(dgr[k]));
-    }
+    HIP_OK(hipFree(dbuf));
     for (int k = 0; k < 3; ++k) {
         HIP_OK(hipFree(dg[k]));
         HIP_OK(hipFree(dl[k]));
