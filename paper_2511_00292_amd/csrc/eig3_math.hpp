@@ -12,6 +12,13 @@
 //          4 J2^3 - 27 J3^2).
 //   lambda Alg. alg:eigvals-stable / Eq. eigvals-trig.
 //
+// Three evaluations of the invariants share the trigonometric tail: FMA (the
+// algorithms above with explicit fused multiply-adds), COMPENSATED (the same
+// algorithms with error-free products and sums throughout) and DOUBLE WORD
+// (J2 and J3 kept unrounded as K2 = 6 J2 and K3 = 27 J3 in double-word
+// arithmetic, Delta from its definition (K2^3 - 2 K3^2) / 54 in double-word
+// arithmetic); the binary32 section at the end adapts them to binary32 data.
+//
 // This file is compiled with -ffp-contract=off: every fused multiply-add is
 // written out, and the error-free transformations below rely on the absence
 // of any other contraction.
